@@ -1,0 +1,144 @@
+"""Invariants of the oracle's full time step: conservation, symmetry, gauge freedom,
+and the single-phase limit (Taylor-Green decay against its closed form)."""
+import numpy as np
+import pytest
+
+from paper_1412_7228_amd import inputs
+
+CS_DROP = dict(eos="cs", T_over_Tc=0.8, A=-0.5, kappa=0.3, s_e=1.2, s_eps=0.9, s_q=1.1, s_nu=1.4)
+RV, RL = 0.02172324, 0.30719570  # CS Maxwell densities at 0.8Tc (checked in test_thermo)
+
+
+def _drop(oracle_mod, nx, ny, R=9.0, seed=0, nthreads=1, **kw):
+    cfg = dict(CS_DROP, nx=nx, ny=ny)
+    cfg.update(kw)
+    o = oracle_mod.Oracle(cfg, nthreads=nthreads)
+    o.init_field(inputs.droplet(nx, ny, R, RL, RV, noise=1e-2, seed=seed))
+    return o
+
+
+def test_mass_and_momentum_conservation(oracle_mod):
+    o = _drop(oracle_mod, 40, 33)
+    ob0 = o.observables()
+    o.run(500)
+    ob = o.observables()
+    assert abs(ob["mass"] / ob0["mass"] - 1) < 1e-13
+    assert abs(ob["mom_x"] - ob0["mom_x"]) < 1e-13 * ob0["mass"]
+    assert abs(ob["mom_y"] - ob0["mom_y"]) < 1e-13 * ob0["mass"]
+    assert ob["n_domain"] == 0 and ob["n_nonfinite"] == 0
+
+
+def test_uniform_state_is_stationary(oracle_mod):
+    o = oracle_mod.Oracle(dict(CS_DROP, nx=7, ny=5))
+    o.init_field(np.full((5, 7), 0.2))
+    f0 = o.f.copy()
+    o.run(50)
+    assert np.abs(o.f - f0).max() < 1e-16
+
+
+def test_translation_equivariance_bitwise(oracle_mod):
+    a = _drop(oracle_mod, 24, 20, R=6)
+    b = oracle_mod.Oracle(a.cfg)
+    b.f = np.ascontiguousarray(np.roll(a.f, (3, -5), axis=(0, 1)))
+    a.run(40)
+    b.run(40)
+    assert np.array_equal(np.roll(a.f, (3, -5), axis=(0, 1)), b.f)
+
+
+# velocity index permutations for the lattice symmetries
+ROT90 = [0, 2, 3, 4, 1, 6, 7, 8, 5]   # e_a rotated by +90 degrees is e_ROT90[a]
+MIRX = [0, 3, 2, 1, 4, 6, 5, 8, 7]    # x -> -x
+
+
+def _rotate_state(f):
+    """Rotate the state by +90 degrees: (x, y) -> (-y, x)."""
+    ny, nx, _ = f.shape
+    g = np.empty((nx, ny, 9))
+    y, x = np.mgrid[0:ny, 0:nx]
+    xn, yn = (-y) % ny, x
+    for a in range(9):
+        g[yn, xn, ROT90[a]] = f[y, x, a]
+    return g
+
+
+def _mirror_state(f):
+    ny, nx, _ = f.shape
+    g = np.empty_like(f)
+    y, x = np.mgrid[0:ny, 0:nx]
+    for a in range(9):
+        g[y, (-x) % nx, MIRX[a]] = f[y, x, a]
+    return g
+
+
+def test_rotation_and_reflection_equivariance(oracle_mod):
+    a = _drop(oracle_mod, 26, 18, R=6, seed=3)
+    r = oracle_mod.Oracle(dict(a.cfg, nx=18, ny=26))
+    r.f = np.ascontiguousarray(_rotate_state(a.f))
+    m = oracle_mod.Oracle(a.cfg)
+    m.f = np.ascontiguousarray(_mirror_state(a.f))
+    a.run(60)
+    r.run(60)
+    m.run(60)
+    scale = np.abs(a.f).max()
+    assert np.abs(_rotate_state(a.f) - r.f).max() < 1e-13 * scale
+    assert np.abs(_mirror_state(a.f) - m.f).max() < 1e-13 * scale
+
+
+def test_interaction_strength_is_a_gauge(oracle_mod):
+    """psi = sqrt(2U/G) makes G psi psi' independent of G < 0."""
+    a = _drop(oracle_mod, 30, 30, R=8, G=-1.0)
+    b = _drop(oracle_mod, 30, 30, R=8, G=-2.5)
+    a.run(200)
+    b.run(200)
+    assert np.abs(a.f - b.f).max() < 1e-12 * np.abs(a.f).max()
+
+
+def test_thread_count_does_not_change_bits(oracle_mod, ncpu):
+    a = _drop(oracle_mod, 31, 29, R=8, nthreads=1)
+    b = _drop(oracle_mod, 31, 29, R=8, nthreads=ncpu)
+    a.run(30)
+    b.run(30)
+    assert np.array_equal(a.f, b.f)
+
+
+def test_kappa_zero_has_no_effect_of_rates_on_conserved_moments(oracle_mod):
+    """s_rho and s_j are immaterial: the oracle's results cannot depend on them."""
+    a = _drop(oracle_mod, 20, 20, R=5)
+    b = _drop(oracle_mod, 20, 20, R=5)
+    b.p.s_rho = 0.3
+    b.p.s_j = 1.7
+    a.run(20)
+    b.run(20)
+    assert np.abs(a.f - b.f).max() < 1e-15
+
+
+def _tg_amplitude(o, n):
+    fl = o.fields()
+    k = 2 * np.pi / n
+    y, x = np.mgrid[0:n, 0:n].astype(float)
+    mode = -np.cos(k * x) * np.sin(k * y)
+    return float(np.sum(fl["ux"] * mode) / np.sum(mode * mode))
+
+
+@pytest.mark.parametrize("s_nu", [1.0, 1.6])
+def test_taylor_green_decay_single_phase(oracle_mod, s_nu):
+    """Ideal EOS switches the interaction off: the vortex decays as exp(-2 nu k^2 t),
+    nu = (1/s_nu - 1/2)/3, with second-order convergence of the decay rate."""
+    nu = (1.0 / s_nu - 0.5) / 3.0
+    errs = []
+    for n in (16, 32, 64):
+        o = oracle_mod.Oracle(dict(nx=n, ny=n, eos="ideal", s_nu=s_nu, s_e=1.1, s_eps=1.2, s_q=1.3),
+                              nthreads=4)
+        rho, ux, uy = inputs.taylor_green(n, u0=1e-3)
+        o.init_field(rho, ux, uy)
+        k = 2 * np.pi / n
+        t_end = int(round(0.5 / (2 * nu * k * k)))
+        o.run(t_end // 4)
+        a1 = _tg_amplitude(o, n)
+        t1 = o.steps
+        o.run(t_end - t1)
+        a2 = _tg_amplitude(o, n)
+        rate = np.log(a1 / a2) / (o.steps - t1)
+        errs.append(abs(rate / (2 * nu * k * k) - 1))
+    assert errs[-1] < 0.01
+    assert errs[0] / errs[1] > 3.0 and errs[1] / errs[2] > 3.0

@@ -1,0 +1,160 @@
+"""Pins of oracle/thermo.py against closed forms, independent formulations and the paper."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import optimize
+
+from oracle import thermo as th
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+
+
+@pytest.mark.parametrize("eos,T", [(th.vdw(0.3), 0.5), (th.carnahan_starling(), 0.08),
+                                   (th.peng_robinson(), 0.06)])
+def test_eos_derivatives_match_finite_differences(eos, T):
+    Tc = 0.0729 if eos.kind == "pr" else None
+    for rho in (0.01, 0.1, 0.3, 0.8 if eos.kind != "cs" else 0.5):
+        h = 1e-5 * rho
+        p = lambda r: float(eos.p(r, T, Tc))
+        d1 = (p(rho + h) - p(rho - h)) / (2 * h)
+        d2 = (p(rho + h) - 2 * p(rho) + p(rho - h)) / h**2
+        assert abs(float(eos.dp(rho, T, Tc)) - d1) < 1e-7 * max(1.0, abs(d1))
+        assert abs(float(eos.d2p(rho, T, Tc)) - d2) < 1e-3 * max(1.0, abs(d2))
+
+
+def test_vdw_critical_point_closed_form():
+    # vdW with a = 9/49, b = 2/21 (Eq. 21): Tc = 8a/(27b) = 4/7, rho_c = 1/(3b) = 3.5
+    rc, Tc = th.critical_point(th.vdw())
+    assert abs(Tc - 4.0 / 7.0) < 1e-15 and abs(rc - 3.5) < 1e-14
+    e = th.vdw()
+    assert abs(float(e.dp(rc, Tc))) < 1e-12 and abs(float(e.d2p(rc, Tc))) < 1e-12
+
+
+def test_cs_critical_point():
+    # textbook Carnahan-Starling critical constants: Tc = 0.3773 a/(b R), rho_c b = 0.5218
+    e = th.carnahan_starling()
+    rc, Tc = th.critical_point(e)
+    assert abs(Tc * 4.0 - 0.3773) < 1e-4
+    assert abs(rc * 4.0 - 0.5218) < 1e-4
+    assert abs(float(e.dp(rc, Tc))) < 1e-12 and abs(float(e.d2p(rc, Tc))) < 1e-9
+
+
+def _coexistence_by_chemical_potential(kind, T):
+    """Independent formulation: equal pressure and equal chemical potential, with mu
+    from the Helmholtz free energy of each EOS (R = 1)."""
+    if kind == "vdw":
+        a, b = 9 / 49, 2 / 21
+        mu = lambda r: T * (math.log(r / (1 - b * r)) + 1 / (1 - b * r)) - 2 * a * r
+        p = lambda r: r * T / (1 - b * r) - a * r * r
+    else:
+        a, b = 1.0, 4.0
+        def mu(r):
+            n = b * r / 4
+            return T * (math.log(r) + (8 * n - 9 * n * n + 3 * n**3) / (1 - n) ** 3) - 2 * a * r
+        p = lambda r: r * T * (1 + (b * r / 4) + (b * r / 4) ** 2 - (b * r / 4) ** 3) / (1 - b * r / 4) ** 3 - a * r * r
+    return p, mu
+
+
+@pytest.mark.parametrize("kind,tr", [("vdw", 0.9), ("cs", 0.8), ("cs", 0.7), ("cs", 0.6)])
+def test_maxwell_matches_chemical_potential_equality(kind, tr):
+    e = th.vdw(0.3) if kind == "vdw" else th.carnahan_starling()
+    _, Tc = th.critical_point(e)
+    T = tr * Tc
+    rv, rl = th.maxwell(e, T)
+    p, mu = _coexistence_by_chemical_potential(kind, T)
+    sol = optimize.fsolve(lambda v: [p(v[0]) - p(v[1]), mu(v[0]) - mu(v[1])], [rv * 1.01, rl * 0.99],
+                          xtol=1e-14)
+    assert abs(sol[0] - rv) < 1e-9 * rl and abs(sol[1] - rl) < 1e-9 * rl
+
+
+def test_vdw_corresponding_states():
+    # reduced vdW coexistence at T_r = 0.9 is universal: rho_l/rho_c = 1.6573, rho_v/rho_c = 0.4257
+    rv, rl = th.maxwell(th.vdw(0.3), 0.9 * 4 / 7)
+    assert abs(rl / 3.5 - 1.6573) < 2e-4 and abs(rv / 3.5 - 0.4257) < 2e-4
+
+
+def test_maxwell_independent_of_K():
+    a = th.maxwell(th.vdw(0.3), 0.9 * 4 / 7)
+    b = th.maxwell(th.vdw(1.0), 0.9 * 4 / 7)
+    assert np.allclose(a, b, rtol=1e-10)
+
+
+def test_discrete_balance_reproduces_table1():
+    g = GOLDEN["table1"]
+    e = th.vdw(0.3)
+    _, Tc = th.critical_point(e)
+    _, rv, rl = th.discrete_flat_balance(e, 0.9 * Tc, -0.5, N=100)
+    assert round(rl, 5) == g["rho_l"] and round(rv, 5) == g["rho_g"]
+
+
+def test_mechanical_stability_close_to_table1():
+    # Eq. (17) is the continuum condition; the lattice densities deviate slightly
+    g = GOLDEN["table1"]
+    e = th.vdw(0.3)
+    _, Tc = th.critical_point(e)
+    rv, rl = th.mechanical_stability(e, 0.9 * Tc, -0.5)
+    assert abs(rv / g["rho_g"] - 1) < 1e-3 and abs(rl / g["rho_l"] - 1) < 1e-4
+    # and it is not the Maxwell construction: the A-dependence is visible
+    mv, ml = th.maxwell(e, 0.9 * Tc)
+    assert abs(mv - rv) > 0.01
+
+
+def test_mechanical_stability_A_half_reduces_to_maxwell_like_limit():
+    # eps = -2A; for A = 0.5 the weight psi'/psi^(1+eps) = psi' , i.e. equal area in psi
+    e = th.vdw(0.3)
+    _, Tc = th.critical_point(e)
+    T = 0.9 * Tc
+    rv, rl = th.mechanical_stability(e, T, 0.5)
+    pc = float(e.p(rv, T))
+    psi = lambda r: math.sqrt(2 * (float(e.p(r, T)) - r / 3) / -1.0)
+    # brute-force check of the equal-area condition in psi on a fine grid
+    r = np.linspace(rv, rl, 400001)
+    ps = np.array([psi(x) for x in r[::100]])
+    pr = np.array([float(e.p(x, T)) for x in r[::100]])
+    area = np.trapezoid(pc - pr, ps)
+    assert abs(area) < 1e-8
+
+
+def test_sigma_leading_order_near_paper():
+    e = th.vdw(0.3)
+    _, Tc = th.critical_point(e)
+    T = 0.9 * Tc
+    g = GOLDEN["sigma_vs_kappa"]
+    s0 = th.sigma_leading_order(e, T, -0.5)
+    assert abs(s0 / g["sigma"][0] - 1) < 0.03
+    ga = GOLDEN["sigma_vs_A"]
+    for A, s in zip(ga["A"], ga["sigma"]):
+        assert abs(th.sigma_leading_order(e, T, A) / s - 1) < 0.05
+    # Eq. (28): linear in (1 - kappa)
+    assert abs(th.sigma_leading_order(e, T, -0.5, kappa=0.9) / s0 - 0.1) < 1e-12
+
+
+def test_gas_density_change_about_25_percent():
+    g = GOLDEN["gas_density_change"]
+    e = th.vdw(0.3)
+    _, Tc = th.critical_point(e)
+    _, rv1, _ = th.discrete_flat_balance(e, 0.9 * Tc, g["A_from"], N=100)
+    _, rv2, _ = th.discrete_flat_balance(e, 0.9 * Tc, g["A_to"], N=100)
+    change = (rv2 - rv1) / rv1
+    assert abs(change - g["relative_change"]) < 0.03
+
+
+def test_lowest_temperature_density_ratios():
+    # Sec. 3.1.2: at its lowest temperature (about 0.69Tc) A = -0.5 has density ratio 22.9;
+    # A = +0.5 stops near 0.79Tc with ratio 16.  The lattice's exact flat balance gives
+    # both ratios; the A = +0.5 gas branch has no solution at 0.69Tc at all.
+    g = GOLDEN["lowest_temperature"]
+    e = th.vdw(0.3)
+    _, Tc = th.critical_point(e)
+    _, rv, rl = th.discrete_flat_balance(e, g["T_over_Tc"][0] * Tc, g["A"][0], N=100)
+    assert abs((rl / rv) / g["density_ratio"][0] - 1) < 0.01
+    ratios = {}
+    for tr in (0.79, 0.80, 0.81):
+        _, rv, rl = th.discrete_flat_balance(e, tr * Tc, g["A"][1], N=100)
+        ratios[tr] = rl / rv
+    assert ratios[0.81] < g["density_ratio"][1] < ratios[0.79]
+    with pytest.raises(RuntimeError):
+        th.discrete_flat_balance(e, 0.69 * Tc, g["A"][1], N=100)
