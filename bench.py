@@ -1,0 +1,171 @@
+#!/usr/bin/env python3
+"""Throughput of the fused pseudo-potential MRT lattice Boltzmann step on one MI355X.
+
+Workload: a single 4096 x 4096 periodic lattice, spinodal decomposition from
+the mean of the Carnahan-Starling coexistence densities at 0.7Tc
+(rho = 0.183713 (1 + 0.01 xi), xi ~ U[-1, 1), seed 0), A = -0.5, kappa = 0,
+FP32 distributions; the FP64 variant is measured beside it.  A step is one
+launch of the fused kernel (density/psi pass, force, pressure-tensor term,
+MRT collision, streaming) over the whole lattice.
+
+Prints ONE JSON line:  value = MLUPS (million lattice updates per second),
+roofline = algorithmic HBM bytes (9 loads + 9 stores per update: 72 B in
+FP32, 144 B in FP64) per launch / measured launch time, against 8 TB/s, and
+cpu_baseline = the FP64 CPU oracle on the host cores on a bounded sample of
+the same lattice.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+N = 4096
+RHO_MEAN = 0.183713  # (rho_v + rho_l)/2 of CS at 0.7Tc: (0.00929415 + 0.35813094)/2
+WORKLOAD = dict(nx=N, ny=N, eos="cs", T_over_Tc=0.7, A=-0.5, kappa=0.0)
+BYTES_PER_LU = {"fp32": 72, "fp64": 144}
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--fp64-steps", type=int, default=500)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--tile", type=str, default="", help="tile_x,tile_y of the step kernel")
+    return ap.parse_args()
+
+
+def time_steps(lat, steps, warmup):
+    """Launch `steps` steps on the lattice's stream bracketed by HIP events on that stream."""
+    import torch
+
+    lat.step(warmup)
+    lat.sync()
+    torch.cuda.synchronize()
+    s = lat.stream
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(s)
+    lat.step(steps)
+    t1.record(s)
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1)  # ms
+
+
+def gpu_measure(precision, steps, warmup, tile):
+    from paper_1412_7228_amd import inputs, lbm
+
+    lat = lbm.Lattice(dict(WORKLOAD, precision=precision))
+    if tile:
+        lat.set_launch(*tile)
+    lat.init_field(inputs.spinodal(N, N, RHO_MEAN, noise=1e-2, seed=0))
+    ms = time_steps(lat, steps, warmup)
+    ob = lat.observables(check=False)
+    lus = float(N * N) * steps
+    per_launch_s = ms * 1e-3 / steps
+    achieved = BYTES_PER_LU[precision] * N * N / per_launch_s / 1e9
+    res = dict(ms_per_step=ms / steps, mlups=lus / (ms * 1e-3) / 1e6, achieved_gbs=achieved,
+               tile=list(lat.launch), mass=ob["mass"], n_nonfinite=ob["n_nonfinite"])
+    lat.close()
+    return res
+
+
+def cpu_baseline(seconds):
+    """The FP64 oracle (as it stands) on the full 4096^2 input, all host cores, as many
+    whole steps as fit in about `seconds`."""
+    import oracle
+    from paper_1412_7228_amd import inputs
+
+    nthr = int(os.environ.get("OMP_NUM_THREADS") or min(16, os.cpu_count() or 1))
+    o = oracle.Oracle(WORKLOAD, nthreads=nthr)
+    o.init_field(inputs.spinodal(N, N, RHO_MEAN, noise=1e-2, seed=0))
+    t = time.perf_counter()
+    o.run(1)
+    one = time.perf_counter() - t
+    k = max(1, min(50, int(seconds / max(one, 1e-3)) - 1))
+    t = time.perf_counter()
+    o.run(k)
+    dt = time.perf_counter() - t
+    return dict(value=N * N * k / dt / 1e6, unit="MLUPS", cores=nthr, kind="oracle",
+                sample=f"4096x4096 lattice (the benchmark's input), {k} FP64 steps after 1 untimed, "
+                       f"{dt:.1f} s on {nthr} threads")
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported (this build has no "
+              "multi-GPU path)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(1)
+    tile = tuple(int(v) for v in a.tile.split(",")) if a.tile else None
+    print(f"[bench] fp32 {N}x{N}: warmup {a.warmup}, timed {a.steps}", file=sys.stderr, flush=True)
+    r32 = gpu_measure("fp32", a.steps, a.warmup, tile)
+    print(f"[bench] fp32 {r32}", file=sys.stderr, flush=True)
+    r64 = None
+    if a.fp64_steps > 0:
+        print(f"[bench] fp64 {N}x{N}: timed {a.fp64_steps}", file=sys.stderr, flush=True)
+        r64 = gpu_measure("fp64", a.fp64_steps, max(10, a.warmup // 4), tile)
+        print(f"[bench] fp64 {r64}", file=sys.stderr, flush=True)
+    cpu = None
+    if not a.no_cpu_baseline:
+        print("[bench] cpu oracle baseline", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(a.cpu_seconds)
+    line = {
+        "metric": "MLUPS and % HBM roofline at 1 MI355X (FP32 vs FP64); runs to hit target sigma",
+        "value": round(r32["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": r32["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "single 4096x4096 periodic lattice, spinodal decomposition, CS EOS, T/Tc=0.7, "
+                        "A=-0.5, kappa=0, FP32 distributions",
+            "lattice": [N, N],
+            "launch_tile": r32["tile"],
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(r32["achieved_gbs"], 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(r32["achieved_gbs"] / HBM_PEAK_GBS, 4),
+            "traffic": None,
+        },
+        "fp64_variant": None if r64 is None else {
+            "value": round(r64["mlups"], 1), "unit": "MLUPS", "steps": a.fp64_steps,
+            "ms_per_step": r64["ms_per_step"],
+            "roofline": {"bound": "hbm", "achieved": round(r64["achieved_gbs"], 1),
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(r64["achieved_gbs"] / HBM_PEAK_GBS, 4)},
+        },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,183 @@
+/*
+ * lbm.h -- C ABI of liblbm, the MI355X (gfx950) implementation of one time
+ * step of the D2Q9 pseudo-potential multiple-relaxation-time lattice
+ * Boltzmann model with Kupershtokh's hybrid interaction force and the
+ * pressure-tensor modification that tunes surface tension independently of
+ * the coexistence densities (Hu, Li & Uddin, arXiv 1412.7228).
+ *
+ * One step (Sec. 2 Eq. 1-10, Sec. 3.2.1 Eq. 23-26):
+ *   rho = sum_a f_a;  U = K p_EOS(rho; T) - rho/3;  psi = sqrt(2U/G)      (Eq. 10)
+ *   F = -A sum_a w_a U(x+e_a) e_a - (1-A) G psi(x) sum_a w_a psi(x+e_a) e_a  (Eq. 9)
+ *   Q = kappa sum_a w_a [(1-A)(G/2) psi (psi(x+e_a)-psi) + (A/2)(U(x+e_a)-U)] e_a e_a (Eq. 23)
+ *   v = (sum_a f_a e_a + F/2) / rho
+ *   m* = m - Lambda (m - m_eq(rho, v)) + (I - Lambda/2) S(v, F) + C(Q)      (Eq. 25)
+ *   f_a(x + e_a, t+1) = (M^{-1} m*)_a(x, t)                                  (Eq. 1)
+ * with w = 1/3 (axis) and 1/12 (diagonal) (Sec. 2, under Eq. 7), m_eq of
+ * Eq. (4), S of Eq. (6) and C of Eq. (26), on a lattice periodic in x and y
+ * (Sec. 3.1.1).  The readings of the printed equations that this library
+ * implements: the last entry of S is vx Fy + vy Fx; the p_xx entry of C is
+ * -s_nu (Qxx - Qyy); Q carries the factor G/2 that Eq. (24) implies; psi is
+ * set to 0 where U > 0 (such cells are counted as domain faults).
+ *
+ * Conventions for every function:
+ *  - Return value: lbm_status, LBM_OK = 0, negative on error.  No function
+ *    aborts or prints; lbm_last_error() gives a message for the calling thread.
+ *  - Host arrays are double precision, nx*ny values, row-major [y][x]
+ *    (x fastest); they are read or written during the call and stay owned by
+ *    the caller.
+ *  - Device state: two distribution buffers (A/B), each 9 planes of
+ *    ny rows of `pitch` elements (pitch = nx rounded up to 64), element type
+ *    double (LBM_FP64) or float (LBM_FP32), plane index a = 0..8 in the
+ *    velocity order e_0=(0,0), e_1=(1,0), e_2=(0,1), e_3=(-1,0), e_4=(0,-1),
+ *    e_5=(1,1), e_6=(-1,1), e_7=(-1,-1), e_8=(1,-1).
+ *  - All device work is enqueued on the context's HIP stream; lbm_step is
+ *    asynchronous, every read-back call synchronises that stream.
+ *  - A context is used by one host thread at a time.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_EINVAL = -1,     /* an argument or parameter is out of range            */
+  LBM_ENOMEM = -2,     /* a device or host allocation failed                  */
+  LBM_EDEVICE = -3,    /* a HIP runtime call failed                           */
+  LBM_ENONFINITE = -4, /* a density that is not finite or not positive        */
+  LBM_EDOMAIN = -5,    /* U > 0 somewhere: psi = sqrt(2U/G) is not real       */
+  LBM_ESTATE = -6      /* call out of order (e.g. step before init)           */
+} lbm_status;
+
+typedef enum {
+  LBM_EOS_IDEAL = 0, /* p = rho/3, so U = 0: no interaction force, no Q            */
+  LBM_EOS_CS = 1,    /* Carnahan-Starling: rho R T (1+n+n^2-n^3)/(1-n)^3 - a rho^2, n = b rho/4 */
+  LBM_EOS_VDW = 2,   /* van der Waals, Eq. (21): rho R T/(1 - b rho) - a rho^2      */
+  LBM_EOS_PR = 3     /* Peng-Robinson, Eq. (29), acentric factor omega_pr          */
+} lbm_eos;
+
+typedef enum { LBM_FP64 = 0, LBM_FP32 = 1 } lbm_precision;
+
+typedef enum {
+  LBM_FIELD_RHO = 0, /* density                                  */
+  LBM_FIELD_UX = 1,  /* velocity (sum f e + F/2)/rho, x component */
+  LBM_FIELD_UY = 2,  /* y component                               */
+  LBM_FIELD_F0 = 3   /* distribution f_a is LBM_FIELD_F0 + a, a = 0..8 */
+} lbm_field;
+
+/* Problem statement: lattice size (Sec. 3.1.1), EOS and temperature
+ * (Eq. 21, Eq. 29), mixing parameter A (Eq. 9), pressure-tensor
+ * coefficient kappa (Eq. 23), relaxation rates (Eq. 2). */
+typedef struct {
+  int32_t nx, ny;     /* periodic lattice, each >= 3                                */
+  int32_t eos;        /* lbm_eos                                                    */
+  int32_t precision;  /* lbm_precision: element type of the distributions           */
+  double a, b, R;     /* EOS constants (b*rho must stay below 1 for vdW/PR, 4 for CS) */
+  double omega_pr;    /* Peng-Robinson acentric factor                              */
+  double K;           /* multiplies the whole EOS pressure (Eq. 21), > 0            */
+  double T_over_Tc;   /* temperature in units of the EOS's critical temperature     */
+  double A;           /* Kupershtokh mixing parameter, Eq. (9)                      */
+  double kappa;       /* pressure-tensor coefficient, Eq. (23)                      */
+  double G;           /* interaction strength, < 0; results do not depend on it     */
+  double s_e, s_eps, s_q, s_nu; /* MRT rates 1/tau of Eq. (2), each in (0, 2);
+                                   s_rho and s_j do not enter (conserved moments)   */
+} lbm_params;
+
+/* FP64 observables of the current state (Sec. 3.1.1, Eq. 22).
+ * rho_in is rho at (nx/2, ny/2), rho_out at (0, 0); p = K p_EOS(rho);
+ * dp = p_in - p_out; R_e = sqrt(sum(rho - rho_out) / (rho_in - rho_out) / pi)
+ * (equimolar radius); sigma = dp * R_e (Laplace law); max_u = max |v|. */
+typedef struct {
+  int64_t step;
+  double mass, mom_x, mom_y, rho_min, rho_max, rho_in, rho_out;
+  double p_in, p_out, dp, R_e, sigma, max_u;
+  int64_t n_nonfinite; /* cells with a non-finite or non-positive density */
+  int64_t n_domain;    /* cells with U > 0                                */
+} lbm_obs;
+
+/* Launch shape of the fused step kernel: a workgroup owns a strip of
+ * tile_x columns and marches over tile_y rows. tile_x in {64, 128, 256};
+ * tile_y >= 1.  0 selects the library default for the lattice. */
+typedef struct {
+  int32_t tile_x, tile_y;
+} lbm_launch;
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Fills *p with: 64 x 64, CS (a=1, b=4, R=1), K=1, T/Tc=0.8, A=-0.5,
+ * kappa=0, G=-1, s_e=s_eps=s_nu=1, s_q=8/7, FP64.  Returns LBM_EINVAL on NULL. */
+lbm_status lbm_params_default(lbm_params* p);
+
+/* Critical temperature of the EOS in *p (K does not change it); *Tc receives it.
+ * LBM_EINVAL for an unknown EOS, IDEAL or non-positive constants. */
+lbm_status lbm_critical_temperature(const lbm_params* p, double* Tc);
+
+/* Bytes of one distribution buffer for these parameters (0 if invalid). */
+size_t lbm_buffer_bytes(const lbm_params* p);
+
+/* Creates a context: validates *p, allocates both distribution buffers
+ * (hipMalloc) and small scratch.  hip_stream is a hipStream_t or NULL (the
+ * library then creates its own).  *out receives the context.
+ * Errors: LBM_EINVAL (parameters), LBM_ENOMEM, LBM_EDEVICE. */
+lbm_status lbm_create(const lbm_params* p, void* hip_stream, lbm_ctx** out);
+
+/* As lbm_create, but the caller provides the two distribution buffers
+ * (device pointers, each at least lbm_buffer_bytes(p) bytes, 256-byte
+ * aligned); they stay owned by the caller and must outlive the context. */
+lbm_status lbm_create_ext(const lbm_params* p, void* hip_stream, void* buf_a, void* buf_b,
+                          size_t buf_bytes, lbm_ctx** out);
+
+/* Releases everything the context owns (not caller buffers).  NULL is a no-op. */
+void lbm_destroy(lbm_ctx* ctx);
+
+/* Sets the launch shape of later steps (see lbm_launch). LBM_EINVAL if invalid. */
+lbm_status lbm_set_launch(lbm_ctx* ctx, const lbm_launch* launch);
+lbm_status lbm_get_launch(const lbm_ctx* ctx, lbm_launch* launch);
+
+/* Initial state f_a = W_a rho [1 + 3 e.u + 4.5 (e.u)^2 - 1.5 u^2] (moments
+ * of Eq. 4), W = 4/9, 1/9, 1/36.  rho is required, ux/uy may be NULL (zero).
+ * Resets the step counter.  LBM_ENONFINITE if a density is not finite or <= 0. */
+lbm_status lbm_init_field(lbm_ctx* ctx, const double* rho, const double* ux, const double* uy);
+
+/* Sets the distributions directly from a host array f[a][y][x] (9*nx*ny
+ * doubles), rounded to the context precision.  Resets the step counter. */
+lbm_status lbm_set_distributions(lbm_ctx* ctx, const double* f);
+
+/* Enqueues n >= 0 time steps on the context stream and returns. */
+lbm_status lbm_step(lbm_ctx* ctx, int64_t n);
+
+/* Computes the observables in FP64 on the device (deterministic reduction
+ * order), synchronises and fills *out.  Returns LBM_ENONFINITE or
+ * LBM_EDOMAIN (after filling *out) if the state holds such cells. */
+lbm_status lbm_observables(lbm_ctx* ctx, lbm_obs* out);
+
+/* Copies one field (lbm_field) of the current state to host out[y][x] in FP64. */
+lbm_status lbm_get_field(lbm_ctx* ctx, int32_t which, double* out);
+
+/* Checkpoint: *len receives the byte size when buf is NULL; otherwise buf
+ * (of *len bytes) receives a header (sizes, precision, step, parameter hash)
+ * followed by the raw distribution buffer.  lbm_load_state restores such a
+ * blob into a context with the same parameters (LBM_EINVAL otherwise). */
+lbm_status lbm_save_state(lbm_ctx* ctx, void* buf, size_t* len);
+lbm_status lbm_load_state(lbm_ctx* ctx, const void* buf, size_t len);
+
+/* Waits for the context stream. */
+lbm_status lbm_sync(lbm_ctx* ctx);
+
+/* Current step count and the device pointer of the buffer that holds the
+ * current state (for callers that time or inspect the device state). */
+lbm_status lbm_state_info(const lbm_ctx* ctx, int64_t* step, const void** f_cur, int32_t* pitch);
+
+const char* lbm_strerror(lbm_status s);
+/* Message of the last error on the calling thread ("" if none). */
+const char* lbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

@@ -1,0 +1,184 @@
+// Device-side building blocks of the pseudo-potential MRT lattice Boltzmann
+// step for gfx950: the equations of state, the pseudo-potential, and the
+// per-cell force + pressure-tensor term + MRT collision.  Included by the
+// step kernels (one lattice, and the batched persistent engine) so that both
+// run the same arithmetic.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "lbm_internal.h"
+
+namespace lbm {
+
+template <typename T> struct V2;
+template <> struct V2<float> { using t = float2; };
+template <> struct V2<double> { using t = double2; };
+
+// Working-precision reciprocal and square root.  FP32 uses the hardware
+// v_rcp_f32 / v_sqrt_f32 (1 ulp); FP64 uses correctly rounded operations.
+__device__ __forceinline__ float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp_(double x) { return 1.0 / x; }
+__device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double sqrt_(double x) { return __builtin_sqrt(x); }
+
+// Constants of one step in working precision T.  Derived combinations are
+// formed on the host in FP64 and rounded once.
+template <typename T>
+struct DevC {
+  T KRT;     // K R T
+  T Ka;      // K a          (PR: K a alpha(T))
+  T b;       // b            (CS: b/4)
+  T b2;      // PR: b^2
+  T twoOverG;
+  T fU, fP;  // force: F = fU * g(U) + fP * psi * g(psi), g = 12 sum_a w_a phi(x+e_a) e_a
+  T kP, kB;  // Q: Qxx = kP psi (S_psi/12 - psi) + kB (S_U/12 - U), etc.
+  T s_e, s_eps, s_q, s_nu;
+  T h_e, h_eps, h_q, h_nu;  // 1 - s/2
+  T c_e;                    // 1.5 s_e   (first non-zero entry of C, Eq. 26)
+};
+
+template <typename T>
+inline DevC<T> make_devc(const ModelConsts& m) {
+  DevC<T> c;
+  c.KRT = T(m.K * m.R * m.T);
+  c.Ka = T(m.eos == LBM_EOS_PR ? m.K * m.aalpha : m.K * m.a);
+  c.b = T(m.eos == LBM_EOS_CS ? m.b / 4.0 : m.b);
+  c.b2 = T(m.b * m.b);
+  c.twoOverG = T(2.0 / m.G);
+  c.fU = T(-m.A / 12.0);
+  c.fP = T(-(1.0 - m.A) * m.G / 12.0);
+  c.kP = T(m.kappa * (1.0 - m.A) * m.G / 2.0);
+  c.kB = T(m.kappa * m.A / 2.0);
+  c.s_e = T(m.s_e);
+  c.s_eps = T(m.s_eps);
+  c.s_q = T(m.s_q);
+  c.s_nu = T(m.s_nu);
+  c.h_e = T(1.0 - 0.5 * m.s_e);
+  c.h_eps = T(1.0 - 0.5 * m.s_eps);
+  c.h_q = T(1.0 - 0.5 * m.s_q);
+  c.h_nu = T(1.0 - 0.5 * m.s_nu);
+  c.c_e = T(1.5 * m.s_e);
+  return c;
+}
+
+// U = K p_EOS(rho) - rho/3  (Eq. 10 with c = 1, c_s^2 = 1/3).
+template <int EOS, typename T>
+__device__ __forceinline__ T eos_U(T rho, const DevC<T>& c) {
+  const T third = T(1) / T(3);
+  if constexpr (EOS == LBM_EOS_CS) {
+    // Carnahan-Starling, n = b rho / 4
+    const T n = c.b * rho;
+    const T om = T(1) - n;
+    const T num = T(1) + n * (T(1) + n * (T(1) - n));
+    const T den = om * om * om;
+    return rho * (c.KRT * num * rcp_(den) - c.Ka * rho) - rho * third;
+  } else if constexpr (EOS == LBM_EOS_VDW) {
+    // Eq. (21)
+    return rho * (c.KRT * rcp_(T(1) - c.b * rho) - c.Ka * rho) - rho * third;
+  } else if constexpr (EOS == LBM_EOS_PR) {
+    // Eq. (29); Ka already holds K a alpha(T)
+    const T q = T(1) + rho * (T(2) * c.b - c.b2 * rho);
+    return rho * (c.KRT * rcp_(T(1) - c.b * rho) - c.Ka * rho * rcp_(q)) - rho * third;
+  } else {
+    return T(0) * rho;  // ideal gas: no interaction
+  }
+}
+
+// psi = sqrt(2U/G), set to 0 where U > 0 (G < 0).
+template <typename T>
+__device__ __forceinline__ T psi_of(T U, const DevC<T>& c) {
+  const T s = c.twoOverG * U;
+  return sqrt_(s > T(0) ? s : T(0));
+}
+
+// One cell: g[9] the distributions at x after streaming (time t), rho their
+// sum, Un/Pn the values of U and psi at x + e_a (index a, a = 0 is x itself).
+// Writes the post-collision distributions f*_a(x) to out[9].
+template <typename T>
+__device__ __forceinline__ void collide_cell(const T (&g)[9], T rho, const T (&Un)[9],
+                                             const T (&Pn)[9], const DevC<T>& c, T (&out)[9]) {
+  // ---- Kupershtokh force, Eq. (9): 12 sum_a w_a phi(x+e_a) e_a, w = 1/3, 1/12
+  const T gUx = T(4) * (Un[1] - Un[3]) + ((Un[5] - Un[7]) + (Un[8] - Un[6]));
+  const T gUy = T(4) * (Un[2] - Un[4]) + ((Un[5] - Un[7]) + (Un[6] - Un[8]));
+  const T gPx = T(4) * (Pn[1] - Pn[3]) + ((Pn[5] - Pn[7]) + (Pn[8] - Pn[6]));
+  const T gPy = T(4) * (Pn[2] - Pn[4]) + ((Pn[5] - Pn[7]) + (Pn[6] - Pn[8]));
+  const T psic = Pn[0], Uc = Un[0];
+  const T fpp = c.fP * psic;
+  const T Fx = c.fU * gUx + fpp * gPx;
+  const T Fy = c.fU * gUy + fpp * gPy;
+
+  // ---- pressure-tensor modification, Eq. (23) with the factor G/2
+  const T t12 = T(1) / T(12);
+  const T dP = (Pn[5] + Pn[7]) + (Pn[6] + Pn[8]);
+  const T dU = (Un[5] + Un[7]) + (Un[6] + Un[8]);
+  const T ka = c.kP * psic;
+  const T Qxx = ka * ((T(4) * (Pn[1] + Pn[3]) + dP) * t12 - psic) +
+                c.kB * ((T(4) * (Un[1] + Un[3]) + dU) * t12 - Uc);
+  const T Qyy = ka * ((T(4) * (Pn[2] + Pn[4]) + dP) * t12 - psic) +
+                c.kB * ((T(4) * (Un[2] + Un[4]) + dU) * t12 - Uc);
+  const T Qxy = (ka * ((Pn[5] + Pn[7]) - (Pn[6] + Pn[8])) +
+                 c.kB * ((Un[5] + Un[7]) - (Un[6] + Un[8]))) * t12;
+
+  // ---- moments m = M f, order (rho, e, eps, jx, qx, jy, qy, pxx, pxy)
+  const T a13 = g[1] + g[3], a24 = g[2] + g[4];
+  const T d13 = g[1] - g[3], d24 = g[2] - g[4];
+  const T sd = (g[5] + g[7]) + (g[6] + g[8]);
+  const T dx = (g[5] - g[7]) + (g[8] - g[6]);
+  const T dy = (g[5] - g[7]) + (g[6] - g[8]);
+  const T s14 = a13 + a24;
+  const T e = T(2) * sd - s14 - T(4) * g[0];
+  const T eps = T(4) * g[0] - T(2) * s14 + sd;
+  const T jx = d13 + dx, jy = d24 + dy;
+  const T qx = dx - T(2) * d13, qy = dy - T(2) * d24;
+  const T pxx = a13 - a24;
+  const T pxy = (g[5] + g[7]) - (g[6] + g[8]);
+
+  // ---- velocity v = (j + F/2)/rho and the collision of Eq. (25)
+  const T mx = jx + T(0.5) * Fx, my = jy + T(0.5) * Fy;  // rho v
+  const T ir = rcp_(rho);
+  const T vx = mx * ir, vy = my * ir;
+  const T v2 = vx * vx + vy * vy;
+  const T vF = vx * Fx + vy * Fy;
+  const T es = e - c.s_e * (e - rho * (T(3) * v2 - T(2))) + c.h_e * (T(6) * vF) + c.c_e * (Qxx + Qyy);
+  const T epss = eps - c.s_eps * (eps - rho * (T(1) - T(3) * v2)) - c.h_eps * (T(6) * vF);
+  const T jxs = jx + Fx, jys = jy + Fy;
+  const T qxs = qx - c.s_q * (qx + mx) - c.h_q * Fx;
+  const T qys = qy - c.s_q * (qy + my) - c.h_q * Fy;
+  const T pxxs = pxx - c.s_nu * (pxx - (mx * vx - my * vy)) +
+                 c.h_nu * (T(2) * (vx * Fx - vy * Fy)) - c.s_nu * (Qxx - Qyy);
+  const T pxys = pxy - c.s_nu * (pxy - mx * vy) + c.h_nu * (vx * Fy + vy * Fx) - c.s_nu * Qxy;
+
+  // ---- f* = M^{-1} m*, M^{-1} = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4)
+  const T r9 = rho * (T(1) / T(9));
+  const T a0 = r9 - es * (T(1) / T(36)) - epss * (T(1) / T(18));
+  const T b0 = r9 + es * (T(1) / T(18)) + epss * (T(1) / T(36));
+  const T Xa = (jxs - qxs) * (T(1) / T(6));
+  const T Ya = (jys - qys) * (T(1) / T(6));
+  const T Xd = jxs * (T(1) / T(6)) + qxs * t12;
+  const T Yd = jys * (T(1) / T(6)) + qys * t12;
+  const T Pq = pxxs * T(0.25), Rq = pxys * T(0.25);
+  out[0] = (rho - es + epss) * (T(1) / T(9));
+  out[1] = a0 + Xa + Pq;
+  out[2] = a0 + Ya - Pq;
+  out[3] = a0 - Xa + Pq;
+  out[4] = a0 - Ya - Pq;
+  out[5] = b0 + (Xd + Yd) + Rq;
+  out[6] = b0 + (Yd - Xd) - Rq;
+  out[7] = b0 - (Xd + Yd) + Rq;
+  out[8] = b0 + (Xd - Yd) - Rq;
+}
+
+// Workgroup -> tile order: the hardware deals workgroups round-robin over the
+// 8 XCDs; renumber so that each XCD receives a contiguous run of tiles
+// (neighbouring row blocks of a strip share their halo rows in that XCD's L2).
+__device__ __forceinline__ int xcd_remap(int b, int n) {
+  const int full = n & ~7;
+  if (b >= full) return b;
+  const int per = full >> 3;
+  return (b & 7) * per + (b >> 3);
+}
+
+__device__ __forceinline__ int wrap_(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+}  // namespace lbm

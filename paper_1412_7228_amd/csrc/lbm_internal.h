@@ -1,0 +1,65 @@
+// Internal interface between the host C ABI (lbm_api.hip) and the gfx950
+// kernels (lbm_step.hip, lbm_fields.hip).  Not installed, not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "lbm.h"
+
+namespace lbm {
+
+// Lattice geometry and the launch shape of the fused step kernel.
+struct Geometry {
+  int nx, ny, pitch;       // elements; pitch = row stride of one plane
+  long long plane;         // ny * pitch elements
+  int tile_x, tile_y;      // strip width (= workgroup size) and rows per workgroup
+  int nstrips, nrowblocks; // ceil(nx / tile_x), ceil(ny / tile_y)
+  int nblocks;             // nstrips * nrowblocks
+};
+
+// Every model constant the step needs, in FP64; the launcher rounds them to
+// the working precision.  Names follow the paper: K (Eq. 21), A (Eq. 9),
+// kappa (Eq. 23), G (Eq. 7), s_* the MRT rates (Eq. 2).
+struct ModelConsts {
+  int eos;                  // lbm_eos
+  double K, R, T, a, b;     // EOS
+  double aalpha;            // Peng-Robinson a * alpha(T)
+  double G, A, kappa;
+  double s_e, s_eps, s_q, s_nu;
+};
+
+// Fused density/psi + force + Q + MRT collision + streaming, one time step:
+// reads f(t) from `fa`, writes f(t+1) to `fb` (separate buffers).
+hipError_t launch_step(lbm_precision prec, const Geometry& g, const ModelConsts& m, const void* fa,
+                       void* fb, hipStream_t s);
+
+// f = equilibrium(rho, u) from device FP64 arrays [ny][nx] (ux/uy may be null).
+hipError_t launch_init_equilibrium(lbm_precision prec, const Geometry& g, const double* rho,
+                                   const double* ux, const double* uy, void* f, hipStream_t s);
+
+// f plane `a` (pitched, working precision) <-> unpadded FP64 [ny][nx].
+hipError_t launch_plane_to_f64(lbm_precision prec, const Geometry& g, const void* f, int a,
+                               double* out, hipStream_t s);
+hipError_t launch_f64_to_plane(lbm_precision prec, const Geometry& g, const double* in, int a,
+                               void* f, hipStream_t s);
+
+// FP64 macroscopic fields of a state: rho, U, psi into `work` (3 * nx*ny doubles).
+hipError_t launch_density_fields(lbm_precision prec, const Geometry& g, const ModelConsts& m,
+                                 const void* f, double* work, hipStream_t s);
+
+// Velocity component (0 = x, 1 = y) into out[ny][nx]; needs the work arrays above.
+hipError_t launch_velocity_field(lbm_precision prec, const Geometry& g, const ModelConsts& m,
+                                 const void* f, const double* work, int comp, double* out,
+                                 hipStream_t s);
+
+// Deterministic FP64 reduction of the observables: fills red[0..kNumRed).
+// `partials` must hold obs_partials_count(g) * kNumRed doubles.
+constexpr int kNumRed = 8;  // mass, mom_x, mom_y, rho_min, rho_max, max|v|, n_domain, n_bad
+int obs_partials_count(const Geometry& g);
+hipError_t launch_observables(lbm_precision prec, const Geometry& g, const ModelConsts& m,
+                              const void* f, const double* work, double* partials, double* red,
+                              hipStream_t s);
+
+}  // namespace lbm

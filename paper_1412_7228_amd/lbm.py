@@ -1,0 +1,253 @@
+"""ctypes binding of liblbm's C ABI (include/lbm.h).
+
+Argument marshalling only: every step of the update runs in the library's HIP
+kernels.  PyTorch provides the device memory (the two distribution buffers are
+torch tensors handed to ``lbm_create_ext``) and the stream (torch's current
+stream by default).  There is no fallback: if ``liblbm.so`` is missing or no
+HIP device is present, constructing a :class:`Lattice` raises.
+
+Parameters are passed as a plain dict with keys ``nx, ny, eos ('ideal'|'cs'|
+'vdw'|'pr'), a, b, R, omega_pr, K, T_over_Tc, A, kappa, G, s_e, s_eps, s_q,
+s_nu, precision ('fp64'|'fp32')``; missing keys take :data:`DEFAULTS`.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbm.so")
+
+EOS = {"ideal": 0, "cs": 1, "vdw": 2, "pr": 3}
+EOS_CONSTANTS = {
+    "ideal": dict(a=1.0, b=1.0, R=1.0),
+    "cs": dict(a=1.0, b=4.0, R=1.0),
+    "vdw": dict(a=9.0 / 49.0, b=2.0 / 21.0, R=1.0),
+    "pr": dict(a=2.0 / 49.0, b=2.0 / 21.0, R=1.0),
+}
+PRECISION = {"fp64": 0, "fp32": 1}
+FIELDS = {"rho": 0, "ux": 1, "uy": 2, **{f"f{a}": 3 + a for a in range(9)}}
+DEFAULTS = dict(eos="cs", K=1.0, T_over_Tc=0.8, A=-0.5, kappa=0.0, G=-1.0, omega_pr=0.344,
+                s_e=1.0, s_eps=1.0, s_q=8.0 / 7.0, s_nu=1.0, precision="fp64")
+
+STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EDEVICE",
+          -4: "LBM_ENONFINITE", -5: "LBM_EDOMAIN", -6: "LBM_ESTATE"}
+
+
+class LBMError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("eos", ctypes.c_int32),
+                ("precision", ctypes.c_int32),
+                ("a", ctypes.c_double), ("b", ctypes.c_double), ("R", ctypes.c_double),
+                ("omega_pr", ctypes.c_double), ("K", ctypes.c_double),
+                ("T_over_Tc", ctypes.c_double), ("A", ctypes.c_double),
+                ("kappa", ctypes.c_double), ("G", ctypes.c_double),
+                ("s_e", ctypes.c_double), ("s_eps", ctypes.c_double), ("s_q", ctypes.c_double),
+                ("s_nu", ctypes.c_double)]
+
+
+class Obs(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_int64)] + [
+        (k, ctypes.c_double) for k in ("mass", "mom_x", "mom_y", "rho_min", "rho_max", "rho_in",
+                                       "rho_out", "p_in", "p_out", "dp", "R_e", "sigma", "max_u")
+    ] + [("n_nonfinite", ctypes.c_int64), ("n_domain", ctypes.c_int64)]
+
+
+class Launch(ctypes.Structure):
+    _fields_ = [("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load liblbm.so and declare its entry points.  Raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError(f"{path} is not built (python -m paper_1412_7228_amd.build)")
+    lib = ctypes.CDLL(path)
+    vp, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)
+    P = ctypes.POINTER(Params)
+    st = ctypes.c_int
+    decl = {
+        "lbm_params_default": (st, [P]),
+        "lbm_critical_temperature": (st, [P, dp]),
+        "lbm_buffer_bytes": (ctypes.c_size_t, [P]),
+        "lbm_create": (st, [P, vp, ctypes.POINTER(vp)]),
+        "lbm_create_ext": (st, [P, vp, vp, vp, ctypes.c_size_t, ctypes.POINTER(vp)]),
+        "lbm_destroy": (None, [vp]),
+        "lbm_set_launch": (st, [vp, ctypes.POINTER(Launch)]),
+        "lbm_get_launch": (st, [vp, ctypes.POINTER(Launch)]),
+        "lbm_init_field": (st, [vp, dp, dp, dp]),
+        "lbm_set_distributions": (st, [vp, dp]),
+        "lbm_step": (st, [vp, ctypes.c_int64]),
+        "lbm_observables": (st, [vp, ctypes.POINTER(Obs)]),
+        "lbm_get_field": (st, [vp, ctypes.c_int32, dp]),
+        "lbm_save_state": (st, [vp, vp, ctypes.POINTER(ctypes.c_size_t)]),
+        "lbm_load_state": (st, [vp, vp, ctypes.c_size_t]),
+        "lbm_sync": (st, [vp]),
+        "lbm_state_info": (st, [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(vp),
+                                ctypes.POINTER(ctypes.c_int32)]),
+        "lbm_strerror": (ctypes.c_char_p, [st]),
+        "lbm_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in decl.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != 0:
+        raise LBMError(status, load_library().lbm_last_error().decode())
+
+
+def make_params(cfg: dict) -> Params:
+    c = dict(DEFAULTS)
+    c.update(cfg)
+    for k, v in EOS_CONSTANTS[c["eos"]].items():
+        c.setdefault(k, v)
+    return Params(int(c["nx"]), int(c["ny"]), EOS[c["eos"]], PRECISION[c["precision"]],
+                  float(c["a"]), float(c["b"]), float(c["R"]), float(c["omega_pr"]),
+                  float(c["K"]), float(c["T_over_Tc"]), float(c["A"]), float(c["kappa"]),
+                  float(c["G"]), float(c["s_e"]), float(c["s_eps"]), float(c["s_q"]),
+                  float(c["s_nu"]))
+
+
+def critical_temperature(cfg: dict) -> float:
+    lib = load_library()
+    p = make_params(dict(cfg, nx=cfg.get("nx", 3), ny=cfg.get("ny", 3)))
+    tc = ctypes.c_double()
+    _check(lib.lbm_critical_temperature(ctypes.byref(p), ctypes.byref(tc)))
+    return tc.value
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+class Lattice:
+    """One periodic lattice on the current HIP device.
+
+    ``stream``: a ``torch.cuda.Stream`` (default: torch's current stream).
+    ``torch_buffers``: allocate the two distribution buffers with torch
+    (default) or let the library ``hipMalloc`` them.
+    """
+
+    def __init__(self, cfg: dict, stream=None, torch_buffers: bool = True):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("liblbm needs a HIP device; none is visible")
+        self.lib = load_library()
+        self.cfg = dict(DEFAULTS, **cfg)
+        self.p = make_params(cfg)
+        self.nx, self.ny = self.p.nx, self.p.ny
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        sp = ctypes.c_void_p(self.stream.cuda_stream)
+        self._bufs = None
+        if torch_buffers:
+            nbytes = self.lib.lbm_buffer_bytes(ctypes.byref(self.p))
+            if nbytes == 0:
+                _check(self.lib.lbm_create(ctypes.byref(self.p), sp, ctypes.byref(h)))
+            self._bufs = [torch.empty(nbytes, dtype=torch.uint8, device="cuda") for _ in range(2)]
+            _check(self.lib.lbm_create_ext(ctypes.byref(self.p), sp,
+                                           ctypes.c_void_p(self._bufs[0].data_ptr()),
+                                           ctypes.c_void_p(self._bufs[1].data_ptr()),
+                                           nbytes, ctypes.byref(h)))
+        else:
+            _check(self.lib.lbm_create(ctypes.byref(self.p), sp, ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.lbm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- launch shape --------------------------------------------------------
+    @property
+    def launch(self) -> tuple[int, int]:
+        l = Launch()
+        _check(self.lib.lbm_get_launch(self.h, ctypes.byref(l)))
+        return l.tile_x, l.tile_y
+
+    def set_launch(self, tile_x: int = 0, tile_y: int = 0):
+        l = Launch(int(tile_x), int(tile_y))
+        _check(self.lib.lbm_set_launch(self.h, ctypes.byref(l)))
+
+    # -- state ---------------------------------------------------------------
+    def init_field(self, rho, ux=None, uy=None):
+        shp = (self.ny, self.nx)
+        r = np.ascontiguousarray(rho, dtype=np.float64).reshape(shp)
+        u = None if ux is None else np.ascontiguousarray(ux, dtype=np.float64).reshape(shp)
+        v = None if uy is None else np.ascontiguousarray(uy, dtype=np.float64).reshape(shp)
+        null = ctypes.POINTER(ctypes.c_double)()
+        _check(self.lib.lbm_init_field(self.h, _dptr(r), _dptr(u) if u is not None else null,
+                                       _dptr(v) if v is not None else null))
+
+    def set_distributions(self, f_soa):
+        f = np.ascontiguousarray(f_soa, dtype=np.float64).reshape(9, self.ny, self.nx)
+        _check(self.lib.lbm_set_distributions(self.h, _dptr(f)))
+
+    def step(self, n: int = 1):
+        _check(self.lib.lbm_step(self.h, int(n)))
+        return self
+
+    def sync(self):
+        _check(self.lib.lbm_sync(self.h))
+
+    # -- read-out ------------------------------------------------------------
+    def observables(self, check: bool = True) -> dict:
+        o = Obs()
+        st = self.lib.lbm_observables(self.h, ctypes.byref(o))
+        if check:
+            _check(st)
+        d = {k: getattr(o, k) for k, _ in Obs._fields_}
+        d["status"] = st
+        return d
+
+    def field(self, name: str) -> np.ndarray:
+        out = np.empty((self.ny, self.nx))
+        _check(self.lib.lbm_get_field(self.h, FIELDS[name], _dptr(out)))
+        return out
+
+    def f_soa(self) -> np.ndarray:
+        return np.stack([self.field(f"f{a}") for a in range(9)])
+
+    def fields(self) -> dict:
+        return {k: self.field(k) for k in ("rho", "ux", "uy")}
+
+    def save_state(self) -> bytes:
+        n = ctypes.c_size_t(0)
+        _check(self.lib.lbm_save_state(self.h, None, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        _check(self.lib.lbm_save_state(self.h, buf, ctypes.byref(n)))
+        return buf.raw[: n.value]
+
+    def load_state(self, blob: bytes):
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        _check(self.lib.lbm_load_state(self.h, buf, len(blob)))
+
+    def info(self) -> dict:
+        step, ptr, pitch = ctypes.c_int64(), ctypes.c_void_p(), ctypes.c_int32()
+        _check(self.lib.lbm_state_info(self.h, ctypes.byref(step), ctypes.byref(ptr),
+                                       ctypes.byref(pitch)))
+        return dict(step=step.value, f_cur=ptr.value, pitch=pitch.value)

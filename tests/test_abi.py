@@ -1,0 +1,87 @@
+"""The C-ABI library without a GPU: it loads, exports every declared entry point,
+validates parameters before touching the device, and its host-side critical
+temperature agrees with the oracle's thermodynamics."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1412_7228_amd import lbm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", fn)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names |= set(re.findall(r"\b(lbm_[a-z0-9_]+)\s*\(", src))
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(lbm.LIB_PATH):
+        from paper_1412_7228_amd import build
+
+        build.build()
+    return lbm.load_library()
+
+
+def test_header_declares_the_core_entry_points():
+    names = declared_symbols()
+    for core in ("lbm_create", "lbm_init_field", "lbm_step", "lbm_observables"):
+        assert core in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    missing = [n for n in declared_symbols() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_defaults_and_strerror(lib):
+    p = lbm.Params()
+    assert lib.lbm_params_default(ctypes.byref(p)) == 0
+    assert (p.nx, p.ny, p.eos, p.precision) == (64, 64, 1, 0)
+    assert lib.lbm_strerror(-4) == b"non-finite or non-positive density"
+    assert lib.lbm_params_default(None) == -1
+
+
+@pytest.mark.parametrize("bad", [dict(nx=2), dict(ny=0), dict(s_nu=2.0), dict(s_e=0.0),
+                                 dict(G=0.5), dict(precision_code=7), dict(eos_code=9),
+                                 dict(K=-1.0), dict(T_over_Tc=0.0)])
+def test_invalid_parameters_are_rejected_before_device_use(lib, bad):
+    cfg = dict(nx=16, ny=16)
+    cfg.update({k: v for k, v in bad.items() if not k.endswith("_code")})
+    p = lbm.make_params(cfg)
+    if "precision_code" in bad:
+        p.precision = bad["precision_code"]
+    if "eos_code" in bad:
+        p.eos = bad["eos_code"]
+    h = ctypes.c_void_p()
+    assert lib.lbm_create(ctypes.byref(p), None, ctypes.byref(h)) == -1
+    assert not h.value
+    assert lib.lbm_last_error() != b""
+    assert lib.lbm_buffer_bytes(ctypes.byref(p)) == 0
+
+
+def test_buffer_bytes_pitch(lib):
+    p = lbm.make_params(dict(nx=100, ny=7, precision="fp32"))
+    assert lib.lbm_buffer_bytes(ctypes.byref(p)) == 9 * 7 * 128 * 4
+    p = lbm.make_params(dict(nx=128, ny=3))
+    assert lib.lbm_buffer_bytes(ctypes.byref(p)) == 9 * 3 * 128 * 8
+
+
+@pytest.mark.parametrize("eos", ["cs", "vdw", "pr"])
+def test_library_critical_temperature_matches_oracle(lib, oracle_mod, eos):
+    tc_lib = lbm.critical_temperature(dict(eos=eos))
+    _, tc_orc = oracle_mod.temperature(dict(eos=eos, T_over_Tc=1.0))
+    assert abs(tc_lib / tc_orc - 1) < 1e-13
+
+
+def test_critical_temperature_rejects_ideal(lib):
+    with pytest.raises(lbm.LBMError):
+        lbm.critical_temperature(dict(eos="ideal"))
