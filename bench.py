@@ -45,7 +45,31 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--tile", type=str, default="", help="tile_x,tile_y of the step kernel")
+    ap.add_argument("--copy-mib", type=int, default=1024,
+                    help="size of the device-to-device copy timed as the practical bandwidth ceiling "
+                         "(0 = skip); under a counter profiler it calibrates FETCH_SIZE/WRITE_SIZE")
     return ap.parse_args()
+
+
+def copy_bandwidth(mib, reps=10):
+    """A plain device copy of `mib` MiB (read + write) on torch's stream: GB/s moved."""
+    import torch
+
+    n = mib * (1 << 20)
+    src = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / reps
+    del src, dst
+    return dict(bytes_per_copy=2 * n, ms=ms, gbs=2 * n / (ms * 1e-3) / 1e9)
 
 
 def time_steps(lat, steps, warmup):
@@ -124,6 +148,10 @@ def main():
         print(f"[bench] fp64 {N}x{N}: timed {a.fp64_steps}", file=sys.stderr, flush=True)
         r64 = gpu_measure("fp64", a.fp64_steps, max(10, a.warmup // 4), tile)
         print(f"[bench] fp64 {r64}", file=sys.stderr, flush=True)
+    copy = None
+    if a.copy_mib > 0:
+        copy = copy_bandwidth(a.copy_mib)
+        print(f"[bench] device copy {copy}", file=sys.stderr, flush=True)
     cpu = None
     if not a.no_cpu_baseline:
         print("[bench] cpu oracle baseline", file=sys.stderr, flush=True)
@@ -163,6 +191,9 @@ def main():
                          "frac": round(r64["achieved_gbs"] / HBM_PEAK_GBS, 4)},
         },
         "cpu_baseline": cpu,
+        "copy_ceiling": None if copy is None else {
+            "gbs": round(copy["gbs"], 1), "bytes": copy["bytes_per_copy"],
+            "note": "device-to-device copy of the same stream, read + write bytes / time"},
     }
     print(json.dumps(line), flush=True)
 

@@ -29,7 +29,12 @@
  *    ny rows of `pitch` elements (pitch = nx rounded up to 64), element type
  *    double (LBM_FP64) or float (LBM_FP32), plane index a = 0..8 in the
  *    velocity order e_0=(0,0), e_1=(1,0), e_2=(0,1), e_3=(-1,0), e_4=(0,-1),
- *    e_5=(1,1), e_6=(-1,1), e_7=(-1,-1), e_8=(1,-1).
+ *    e_5=(1,1), e_6=(-1,1), e_7=(-1,-1), e_8=(1,-1).  A buffer holds the
+ *    post-collision distributions of the previous step before streaming (the
+ *    step kernel streams by pulling), so f_a(x, y) of the current state is
+ *    the element (x - e_ax, y - e_ay) (periodic) of plane a.  Every host-side
+ *    value (fields, distributions, observables, initial data) is the streamed
+ *    state f(x, t) of Eq. (1).
  *  - All device work is enqueued on the context's HIP stream; lbm_step is
  *    asynchronous, every read-back call synchronises that stream.
  *  - A context is used by one host thread at a time.
@@ -74,7 +79,8 @@ typedef enum {
  * (Eq. 21, Eq. 29), mixing parameter A (Eq. 9), pressure-tensor
  * coefficient kappa (Eq. 23), relaxation rates (Eq. 2). */
 typedef struct {
-  int32_t nx, ny;     /* periodic lattice, each >= 3                                */
+  int32_t nx, ny;     /* periodic lattice, each >= 3; one plane (ny * pitch elements)
+                         must stay below 4 GiB                                     */
   int32_t eos;        /* lbm_eos                                                    */
   int32_t precision;  /* lbm_precision: element type of the distributions           */
   double a, b, R;     /* EOS constants (b*rho must stay below 1 for vdW/PR, 4 for CS) */
@@ -117,12 +123,19 @@ lbm_status lbm_params_default(lbm_params* p);
  * LBM_EINVAL for an unknown EOS, IDEAL or non-positive constants. */
 lbm_status lbm_critical_temperature(const lbm_params* p, double* Tc);
 
+/* Maxwell equal-area coexistence densities of the EOS in *p at T_over_Tc
+ * (0 < T/Tc < 1; K does not change them), for initial fields.  The model's
+ * own steady densities deviate from these by the A-dependent amount of
+ * Eq. (17).  LBM_EINVAL for IDEAL, T/Tc outside (0, 1) or no bracket. */
+lbm_status lbm_coexistence(const lbm_params* p, double* rho_v, double* rho_l);
+
 /* Bytes of one distribution buffer for these parameters (0 if invalid). */
 size_t lbm_buffer_bytes(const lbm_params* p);
 
 /* Creates a context: validates *p, allocates both distribution buffers
- * (hipMalloc) and small scratch.  hip_stream is a hipStream_t or NULL (the
- * library then creates its own).  *out receives the context.
+ * (hipMalloc) and small scratch.  hip_stream is the hipStream_t on which all
+ * of the context's device work is enqueued; NULL is the HIP null stream.  The
+ * stream stays owned by the caller.  *out receives the context.
  * Errors: LBM_EINVAL (parameters), LBM_ENOMEM, LBM_EDEVICE. */
 lbm_status lbm_create(const lbm_params* p, void* hip_stream, lbm_ctx** out);
 

@@ -142,12 +142,106 @@ lbm_status critical_temperature(const lbm_params& p, double* Tc) {
   return LBM_OK;
 }
 
+// Maxwell construction at T: coexisting (rho_v, rho_l) with equal pressure
+// and equal area  int_{rho_v}^{rho_l} (p - P)/rho^2 drho = 0.
+double eos_p1(const lbm_params& p, double aalpha, double T, double rho) {
+  return eos_pressure(p.eos, aalpha, p.b, p.R, 1.0, T, p.a, rho);
+}
+
+double eos_dp1(const lbm_params& p, double aalpha, double T, double rho) {
+  // slope at temperature T (PR with alpha(T) through a -> a alpha)
+  return eos_slope(p.eos, p.eos == LBM_EOS_PR ? aalpha : p.a, p.b, p.R, T, rho);
+}
+
+template <typename F>
+double bisect(F f, double lo, double hi, int iters = 200) {
+  double flo = f(lo);
+  for (int it = 0; it < iters && hi - lo > 1e-16 * std::fabs(hi); ++it) {
+    const double mid = 0.5 * (lo + hi);
+    const double fm = f(mid);
+    if ((fm < 0.0) == (flo < 0.0)) { lo = mid; flo = fm; } else { hi = mid; }
+  }
+  return 0.5 * (lo + hi);
+}
+
+// 64-point Gauss-Legendre on [a, b] split into n panels.
+template <typename F>
+double integrate(F f, double a, double b, int n = 64) {
+  static const double xg[8] = {0.0950125098376374, 0.2816035507792589, 0.4580167776572274,
+                               0.6178762444026438, 0.7554044083550030, 0.8656312023878318,
+                               0.9445750230732326, 0.9894009349916499};
+  static const double wg[8] = {0.1894506104550685, 0.1826034150449236, 0.1691565193950025,
+                               0.1495959888165767, 0.1246289712555339, 0.0951585116824928,
+                               0.0622535239386479, 0.0271524594117541};
+  double s = 0.0;
+  const double h = (b - a) / n;
+  for (int k = 0; k < n; ++k) {
+    const double c = a + (k + 0.5) * h, r = 0.5 * h;
+    for (int i = 0; i < 8; ++i) s += wg[i] * r * (f(c - r * xg[i]) + f(c + r * xg[i]));
+  }
+  return s;
+}
+
+lbm_status coexistence(const lbm_params& p, double* rv, double* rl) {
+  double Tc = 0.0;
+  lbm_status st = critical_temperature(p, &Tc);
+  if (st != LBM_OK) return st;
+  if (!(p.T_over_Tc > 0.0 && p.T_over_Tc < 1.0))
+    return fail(LBM_EINVAL, "coexistence needs 0 < T/Tc < 1 (got %g)", p.T_over_Tc);
+  const double T = p.T_over_Tc * Tc;
+  const double aalpha = p.eos == LBM_EOS_PR ? p.a * pr_alpha(p.omega_pr, p.T_over_Tc) : p.a;
+  // spinodal densities around the minimum of dp/drho
+  double rmin = 0.0;
+  {
+    double lo = 1e-6 * max_density(p.eos, p.b), hi = 0.9 * max_density(p.eos, p.b);
+    const double gr = 0.5 * (std::sqrt(5.0) - 1.0);
+    double c = hi - gr * (hi - lo), d = lo + gr * (hi - lo);
+    double fc = eos_dp1(p, aalpha, T, c), fd = eos_dp1(p, aalpha, T, d);
+    for (int it = 0; it < 200 && (hi - lo) > 1e-14 * hi; ++it) {
+      if (fc < fd) { hi = d; d = c; fd = fc; c = hi - gr * (hi - lo); fc = eos_dp1(p, aalpha, T, c); }
+      else { lo = c; c = d; fc = fd; d = lo + gr * (hi - lo); fd = eos_dp1(p, aalpha, T, d); }
+    }
+    rmin = 0.5 * (lo + hi);
+    if (!(eos_dp1(p, aalpha, T, rmin) < 0.0)) return fail(LBM_EINVAL, "no two-phase region at T/Tc = %g", p.T_over_Tc);
+  }
+  const double top = 0.999 * max_density(p.eos, p.b);
+  auto slope = [&](double r) { return eos_dp1(p, aalpha, T, r); };
+  const double s_lo = bisect(slope, 1e-9 * top, rmin);
+  const double s_hi = bisect(slope, rmin, top);
+  const double p_max = eos_p1(p, aalpha, T, s_lo), p_min = std::max(eos_p1(p, aalpha, T, s_hi), 0.0);
+  auto branches = [&](double P, double* v, double* l) {
+    // the vapour branch starts below the ideal-gas density P/(R T)
+    *v = bisect([&](double r) { return eos_p1(p, aalpha, T, r) - P; }, 1e-3 * P / (p.R * T), s_lo);
+    *l = bisect([&](double r) { return eos_p1(p, aalpha, T, r) - P; }, s_hi, top);
+  };
+  // in s = ln(rho): int (p - P)/rho^2 drho = int (p - P)/rho ds, smooth near a dilute vapour
+  auto area = [&](double P) {
+    double v, l;
+    branches(P, &v, &l);
+    return integrate([&](double sv) {
+      const double r = std::exp(sv);
+      return (eos_p1(p, aalpha, T, r) - P) / r;
+    }, std::log(v), std::log(l), 256);
+  };
+  // the area falls as P rises; bracket [p_min, p_max]
+  const double plo = p_min > 0.0 ? p_min * (1.0 + 1e-12) : 1e-12 * p_max, phi = p_max * (1.0 - 1e-12);
+  if (!(area(plo) > 0.0 && area(phi) < 0.0)) return fail(LBM_EINVAL, "Maxwell construction: no bracket");
+  const double Ps = bisect(area, plo, phi, 120);
+  branches(Ps, rv, rl);
+  return LBM_OK;
+}
+
 lbm_status validate(const lbm_params* p) {
   if (!p) return fail(LBM_EINVAL, "params is NULL");
   if (p->nx < 3 || p->ny < 3) return fail(LBM_EINVAL, "lattice %d x %d: each side must be >= 3", p->nx, p->ny);
-  if ((long long)p->nx * p->ny > (1ll << 34)) return fail(LBM_EINVAL, "lattice too large");
   if (p->precision != LBM_FP64 && p->precision != LBM_FP32)
     return fail(LBM_EINVAL, "unknown precision %d", p->precision);
+  // one distribution plane must stay below 4 GiB (32-bit buffer offsets)
+  const unsigned long long plane_bytes = (unsigned long long)p->ny * ((p->nx + 63) / 64 * 64) *
+                                         (p->precision == LBM_FP32 ? 4u : 8u);
+  if (plane_bytes >= (1ull << 32))
+    return fail(LBM_EINVAL, "lattice %d x %d too large: one plane is %llu bytes (limit 4 GiB)",
+                p->nx, p->ny, plane_bytes);
   if (p->eos < LBM_EOS_IDEAL || p->eos > LBM_EOS_PR) return fail(LBM_EINVAL, "unknown EOS %d", p->eos);
   const double rates[4] = {p->s_e, p->s_eps, p->s_q, p->s_nu};
   for (double s : rates)
@@ -260,14 +354,8 @@ lbm_status make_ctx(const lbm_params* p, void* stream, void* ba, void* bb, size_
   c->buf_bytes = 9 * (size_t)c->g.plane * elem_size(*p);
   c->step = 0;
   c->cur = 0;
-  if (stream) {
-    c->stream = static_cast<hipStream_t>(stream);
-    c->own_stream = false;
-  } else {
-    hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
-    if (e != hipSuccess) { delete c; return fail(LBM_EDEVICE, "hipStreamCreate: %s", hipGetErrorString(e)); }
-    c->own_stream = true;
-  }
+  c->stream = static_cast<hipStream_t>(stream);  // NULL is the HIP null stream
+  c->own_stream = false;
   if (ba) {
     if (!bb || bytes < c->buf_bytes || ((uintptr_t)ba & 255) || ((uintptr_t)bb & 255)) {
       lbm_destroy(c);
@@ -324,6 +412,13 @@ lbm_status lbm_critical_temperature(const lbm_params* p, double* Tc) {
   return critical_temperature(*p, Tc);
 }
 
+lbm_status lbm_coexistence(const lbm_params* p, double* rho_v, double* rho_l) {
+  if (!p || !rho_v || !rho_l) return fail(LBM_EINVAL, "NULL argument");
+  if (p->eos == LBM_EOS_IDEAL) return fail(LBM_EINVAL, "ideal gas has no coexistence");
+  if (!(p->a > 0.0 && p->b > 0.0 && p->R > 0.0)) return fail(LBM_EINVAL, "EOS constants must be positive");
+  return coexistence(*p, rho_v, rho_l);
+}
+
 size_t lbm_buffer_bytes(const lbm_params* p) {
   if (validate(p) != LBM_OK) return 0;
   return 9 * (size_t)p->ny * pitch_of(*p) * elem_size(*p);
@@ -341,14 +436,14 @@ lbm_status lbm_create_ext(const lbm_params* p, void* hip_stream, void* buf_a, vo
 
 void lbm_destroy(lbm_ctx* c) {
   if (!c) return;
-  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  (void)hipStreamSynchronize(c->stream);
   if (c->own_buf)
     for (int i = 0; i < 2; ++i)
       if (c->buf[i]) (void)hipFree(c->buf[i]);
   if (c->work) (void)hipFree(c->work);
   if (c->partials) (void)hipFree(c->partials);
   if (c->red) (void)hipFree(c->red);
-  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
 

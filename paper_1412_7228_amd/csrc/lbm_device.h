@@ -158,7 +158,6 @@ __device__ __forceinline__ void collide_cell(const T (&g)[9], T rho, const T (&U
   const T Xd = jxs * (T(1) / T(6)) + qxs * t12;
   const T Yd = jys * (T(1) / T(6)) + qys * t12;
   const T Pq = pxxs * T(0.25), Rq = pxys * T(0.25);
-  out[0] = (rho - es + epss) * (T(1) / T(9));
   out[1] = a0 + Xa + Pq;
   out[2] = a0 + Ya - Pq;
   out[3] = a0 - Xa + Pq;
@@ -167,6 +166,19 @@ __device__ __forceinline__ void collide_cell(const T (&g)[9], T rho, const T (&U
   out[6] = b0 + (Yd - Xd) - Rq;
   out[7] = b0 - (Xd + Yd) + Rq;
   out[8] = b0 + (Xd - Yd) - Rq;
+  // f*_0 from the mass balance of the cell: the nine stored values then sum to
+  // the arriving density up to one rounding, so neither the rounded constants
+  // of M^{-1} nor the rounding of sums of nearly equal populations can create
+  // or destroy mass.  FP32 balances in FP64 (exact for nine FP32 values).
+  if constexpr (sizeof(T) == 4) {
+    const double rin = ((double)g[0] + (((double)g[1] + (double)g[3]) + ((double)g[2] + (double)g[4]))) +
+                       (((double)g[5] + (double)g[7]) + ((double)g[6] + (double)g[8]));
+    const double sout = (((double)out[1] + (double)out[2]) + ((double)out[3] + (double)out[4])) +
+                        (((double)out[5] + (double)out[6]) + ((double)out[7] + (double)out[8]));
+    out[0] = (T)(rin - sout);
+  } else {
+    out[0] = rho - (((out[1] + out[2]) + (out[3] + out[4])) + ((out[5] + out[6]) + (out[7] + out[8])));
+  }
 }
 
 // Workgroup -> tile order: the hardware deals workgroups round-robin over the
@@ -180,5 +192,15 @@ __device__ __forceinline__ int xcd_remap(int b, int n) {
 }
 
 __device__ __forceinline__ int wrap_(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+// The buffers hold the post-collision distributions of the previous step,
+// not yet streamed (the step kernel streams by pulling).  The distribution
+// f_a(x, y) of the current state therefore sits at (x - e_a, y - e_a) of
+// plane a.  Element index of f_a(x, y):
+__device__ __forceinline__ long long state_index(const Geometry& g, int a, int x, int y) {
+  const int ex = (a == 1 || a == 5 || a == 8) ? 1 : ((a == 3 || a == 6 || a == 7) ? -1 : 0);
+  const int ey = (a == 2 || a == 5 || a == 6) ? 1 : ((a == 4 || a == 7 || a == 8) ? -1 : 0);
+  return a * g.plane + (long long)wrap_(y - ey, g.ny) * g.pitch + wrap_(x - ex, g.nx);
+}
 
 }  // namespace lbm

@@ -9,7 +9,7 @@ namespace lbm {
 constexpr int kRedThreads = 256;
 constexpr int kRedCellsPerThread = 16;
 
-// rho = sum_a f_a(x) (the state after streaming), U and psi in FP64.
+// rho = sum_a f_a(x) of the current (streamed) state, U and psi in FP64.
 template <typename T, int EOS>
 __global__ void k_density_fields(const T* __restrict__ f, const Geometry geo, const DevC<double> c,
                                  double* __restrict__ work) {
@@ -17,10 +17,9 @@ __global__ void k_density_fields(const T* __restrict__ f, const Geometry geo, co
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int y = (int)(i / geo.nx), x = (int)(i - (long long)y * geo.nx);
-  const T* src = f + (long long)y * geo.pitch + x;
   double r = 0.0;
 #pragma unroll
-  for (int a = 0; a < 9; ++a) r += (double)src[a * geo.plane];
+  for (int a = 0; a < 9; ++a) r += (double)f[state_index(geo, a, x, y)];
   const double U = eos_U<EOS>(r, c);
   work[i] = r;
   work[n + i] = U;
@@ -46,10 +45,9 @@ __device__ inline void force_and_momentum(const T* __restrict__ f, const Geometr
   const double fpp = c.fP * psi[rc + x];
   Fx = c.fU * gUx + fpp * gPx;
   Fy = c.fU * gUy + fpp * gPy;
-  const T* src = f + (long long)y * geo.pitch + x;
   double g[9];
 #pragma unroll
-  for (int a = 0; a < 9; ++a) g[a] = (double)src[a * geo.plane];
+  for (int a = 0; a < 9; ++a) g[a] = (double)f[state_index(geo, a, x, y)];
   jx = (g[1] - g[3]) + ((g[5] - g[7]) + (g[8] - g[6]));
   jy = (g[2] - g[4]) + ((g[5] - g[7]) + (g[6] - g[8]));
 }
@@ -156,7 +154,7 @@ __global__ void k_plane_to_f64(const T* __restrict__ f, const Geometry geo, int 
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int y = (int)(i / geo.nx), x = (int)(i - (long long)y * geo.nx);
-  out[i] = (double)f[a * geo.plane + (long long)y * geo.pitch + x];
+  out[i] = (double)f[state_index(geo, a, x, y)];
 }
 
 template <typename T>
@@ -166,7 +164,7 @@ __global__ void k_f64_to_plane(const double* __restrict__ in, const Geometry geo
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int y = (int)(i / geo.nx), x = (int)(i - (long long)y * geo.nx);
-  f[a * geo.plane + (long long)y * geo.pitch + x] = T(in[i]);
+  f[state_index(geo, a, x, y)] = T(in[i]);
 }
 
 static dim3 cells_grid(const Geometry& g) {

@@ -19,21 +19,73 @@
 
 namespace lbm {
 
-// f_a(x - e_a) for the 9 velocities, gathered at row r and column x.
-// ro_* are the row offsets (elements) of rows r (rr), r - 1 (rm) and r + 1 (rp).
+// Buffer resource of one distribution plane (gfx9 raw buffer, 32-bit
+// offsets).  Loads through it take the row offset in a scalar register and
+// the column offset in a vector register, so no per-lane 64-bit address
+// arithmetic is needed; an offset past the plane reads 0 instead of faulting.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* base, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, 0x00020000);
+}
+
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+
 template <typename T>
-__device__ __forceinline__ void gather(const T* __restrict__ fa, long long P, long long rr,
-                                       long long rm, long long rp, int x, int xm, int xp,
+__device__ __forceinline__ T ld(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+  } else {
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, T v) {
+  if constexpr (sizeof(T) == 4) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)voff, (int)soff, 0);
+  } else {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)voff, (int)soff, 0);
+  }
+}
+
+// The distribution buffers as seen by the step kernel.  A buffer below 4 GiB
+// is one resource and the plane offset goes into the scalar offset; a larger
+// one gets one resource per plane.
+template <bool BIG>
+struct Planes {
+  __amdgpu_buffer_rsrc_t r[BIG ? 9 : 1];
+  unsigned plane_bytes;
+  __device__ __forceinline__ void init(const void* base, unsigned long long plane_b) {
+    if constexpr (BIG) {
+#pragma unroll
+      for (int a = 0; a < 9; ++a)
+        r[a] = plane_rsrc(static_cast<const char*>(base) + a * plane_b, (unsigned)plane_b);
+    } else {
+      r[0] = plane_rsrc(base, (unsigned)(9 * plane_b));
+    }
+    plane_bytes = (unsigned)plane_b;
+  }
+  __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(int a) const { return r[BIG ? a : 0]; }
+  __device__ __forceinline__ unsigned soff(int a, unsigned row) const {
+    return BIG ? row : a * plane_bytes + row;
+  }
+};
+
+// f_a(x - e_a) for the 9 velocities, gathered at row r.  rr, rm, rp are the
+// byte offsets of rows r, r - 1, r + 1 within a plane (uniform); ox, oxm, oxp
+// the byte offsets of columns x, x - 1, x + 1 (per lane).
+template <typename T, bool BIG>
+__device__ __forceinline__ void gather(const Planes<BIG>& pa, unsigned rr, unsigned rm,
+                                       unsigned rp, unsigned ox, unsigned oxm, unsigned oxp,
                                        T (&g)[9]) {
-  g[0] = fa[0 * P + rr + x];
-  g[1] = fa[1 * P + rr + xm];  // e_1 = ( 1, 0)
-  g[2] = fa[2 * P + rm + x];   // e_2 = ( 0, 1)
-  g[3] = fa[3 * P + rr + xp];  // e_3 = (-1, 0)
-  g[4] = fa[4 * P + rp + x];   // e_4 = ( 0,-1)
-  g[5] = fa[5 * P + rm + xm];  // e_5 = ( 1, 1)
-  g[6] = fa[6 * P + rm + xp];  // e_6 = (-1, 1)
-  g[7] = fa[7 * P + rp + xp];  // e_7 = (-1,-1)
-  g[8] = fa[8 * P + rp + xm];  // e_8 = ( 1,-1)
+  g[0] = ld<T>(pa.rsrc(0), ox, pa.soff(0, rr));
+  g[1] = ld<T>(pa.rsrc(1), oxm, pa.soff(1, rr));  // e_1 = ( 1, 0)
+  g[2] = ld<T>(pa.rsrc(2), ox, pa.soff(2, rm));   // e_2 = ( 0, 1)
+  g[3] = ld<T>(pa.rsrc(3), oxp, pa.soff(3, rr));  // e_3 = (-1, 0)
+  g[4] = ld<T>(pa.rsrc(4), ox, pa.soff(4, rp));   // e_4 = ( 0,-1)
+  g[5] = ld<T>(pa.rsrc(5), oxm, pa.soff(5, rm));  // e_5 = ( 1, 1)
+  g[6] = ld<T>(pa.rsrc(6), oxp, pa.soff(6, rm));  // e_6 = (-1, 1)
+  g[7] = ld<T>(pa.rsrc(7), oxp, pa.soff(7, rp));  // e_7 = (-1,-1)
+  g[8] = ld<T>(pa.rsrc(8), oxm, pa.soff(8, rp));  // e_8 = ( 1,-1)
 }
 
 template <typename T>
@@ -41,7 +93,7 @@ __device__ __forceinline__ T density(const T (&g)[9]) {
   return g[0] + ((g[1] + g[3]) + (g[2] + g[4])) + ((g[5] + g[7]) + (g[6] + g[8]));
 }
 
-template <typename T, int EOS, int BX>
+template <typename T, int EOS, int BX, bool BIG>
 __global__ void __launch_bounds__(BX) k_step(const T* __restrict__ fa, T* __restrict__ fb,
                                               const Geometry geo, const DevC<T> c) {
   using T2 = typename V2<T>::t;
@@ -58,32 +110,40 @@ __global__ void __launch_bounds__(BX) k_step(const T* __restrict__ fa, T* __rest
   const int tx = threadIdx.x;
   const bool active = tx < W;
   const int x = x0 + (active ? tx : W - 1);  // idle lanes gather a valid column
-  const int xm = (x == 0) ? nx - 1 : x - 1;
-  const int xp = (x == nx - 1) ? 0 : x + 1;
+  const unsigned sz = sizeof(T);
+  const unsigned ox = x * sz;
+  const unsigned oxm = ((x == 0) ? nx - 1 : x - 1) * sz;
+  const unsigned oxp = ((x == nx - 1) ? 0 : x + 1) * sz;
   // lanes 0 and 1 also produce the strip's left / right edge column
   const bool edge = tx < 2;
   const int hx = (tx == 0) ? (x0 == 0 ? nx - 1 : x0 - 1) : (x0 + W == nx ? 0 : x0 + W);
-  const int hxm = (hx == 0) ? nx - 1 : hx - 1;
-  const int hxp = (hx == nx - 1) ? 0 : hx + 1;
+  const unsigned ohx = hx * sz;
+  const unsigned ohxm = ((hx == 0) ? nx - 1 : hx - 1) * sz;
+  const unsigned ohxp = ((hx == nx - 1) ? 0 : hx + 1) * sz;
   const int hslot = (tx == 0) ? 0 : W + 1;
+
+  const unsigned row_bytes = (unsigned)(pitch * sz);
+  Planes<BIG> pa, pb;
+  pa.init(fa, (unsigned long long)P * sz);
+  pb.init(fb, (unsigned long long)P * sz);
 
   T fc[9];
   T rho_c = T(0);
 #pragma unroll 1
   for (int i = 0; i < H + 2; ++i) {
     const int r = y0 - 1 + i;
-    const long long rr = wrap_(r, ny) * pitch;
-    const long long rm = wrap_(r - 1, ny) * pitch;
-    const long long rp = wrap_(r + 1, ny) * pitch;
+    const unsigned rr = wrap_(r, ny) * row_bytes;
+    const unsigned rm = wrap_(r - 1, ny) * row_bytes;
+    const unsigned rp = wrap_(r + 1, ny) * row_bytes;
     T g[9];
-    gather(fa, P, rr, rm, rp, x, xm, xp, g);
+    gather(pa, rr, rm, rp, ox, oxm, oxp, g);
     const T rho = density(g);
     const T U = eos_U<EOS>(rho, c);
     const int slot = i & 3;
     if (active) ring[slot][tx + 1] = T2{U, psi_of(U, c)};
     if (edge) {
       T h[9];
-      gather(fa, P, rr, rm, rp, hx, hxm, hxp, h);
+      gather(pa, rr, rm, rp, ohx, ohxm, ohxp, h);
       const T Uh = eos_U<EOS>(density(h), c);
       ring[slot][hslot] = T2{Uh, psi_of(Uh, c)};
     }
@@ -104,9 +164,9 @@ __global__ void __launch_bounds__(BX) k_step(const T* __restrict__ fa, T* __rest
       v = ring[ss][tx + 2]; Un[8] = v.x; Pn[8] = v.y;  // ( 1,-1)
       T out[9];
       collide_cell(fc, rho_c, Un, Pn, c, out);
-      T* dst = fb + (long long)(r - 1) * pitch + x;
+      const unsigned ro = (unsigned)(r - 1) * row_bytes;
 #pragma unroll
-      for (int a = 0; a < 9; ++a) dst[a * P] = out[a];
+      for (int a = 0; a < 9; ++a) st<T>(pb.rsrc(a), ox, pb.soff(a, ro), out[a]);
     }
 #pragma unroll
     for (int a = 0; a < 9; ++a) fc[a] = g[a];
@@ -114,25 +174,34 @@ __global__ void __launch_bounds__(BX) k_step(const T* __restrict__ fa, T* __rest
   }
 }
 
-template <typename T, int EOS>
-static hipError_t launch_step_t(const Geometry& g, const DevC<T>& c, const void* fa, void* fb,
+template <typename T, int EOS, bool BIG>
+static hipError_t launch_step_b(const Geometry& g, const DevC<T>& c, const void* fa, void* fb,
                                 hipStream_t s) {
   const T* a = static_cast<const T*>(fa);
   T* b = static_cast<T*>(fb);
   switch (g.tile_x) {
     case 64:
-      hipLaunchKernelGGL((k_step<T, EOS, 64>), dim3(g.nblocks), dim3(64), 0, s, a, b, g, c);
+      hipLaunchKernelGGL((k_step<T, EOS, 64, BIG>), dim3(g.nblocks), dim3(64), 0, s, a, b, g, c);
       break;
     case 128:
-      hipLaunchKernelGGL((k_step<T, EOS, 128>), dim3(g.nblocks), dim3(128), 0, s, a, b, g, c);
+      hipLaunchKernelGGL((k_step<T, EOS, 128, BIG>), dim3(g.nblocks), dim3(128), 0, s, a, b, g, c);
       break;
     case 256:
-      hipLaunchKernelGGL((k_step<T, EOS, 256>), dim3(g.nblocks), dim3(256), 0, s, a, b, g, c);
+      hipLaunchKernelGGL((k_step<T, EOS, 256, BIG>), dim3(g.nblocks), dim3(256), 0, s, a, b, g, c);
       break;
     default:
       return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+template <typename T, int EOS>
+static hipError_t launch_step_t(const Geometry& g, const DevC<T>& c, const void* fa, void* fb,
+                                hipStream_t s) {
+  const unsigned long long bytes = 9ull * (unsigned long long)g.plane * sizeof(T);
+  if (bytes < (1ull << 32)) return launch_step_b<T, EOS, false>(g, c, fa, fb, s);
+  if ((unsigned long long)g.plane * sizeof(T) >= (1ull << 32)) return hipErrorInvalidValue;
+  return launch_step_b<T, EOS, true>(g, c, fa, fb, s);
 }
 
 template <typename T>
@@ -155,7 +224,8 @@ hipError_t launch_step(lbm_precision prec, const Geometry& g, const ModelConsts&
 }
 
 // ---------------------------------------------------------------------------
-// Initial state: f_a = W_a rho [1 + 3 e.u + 4.5 (e.u)^2 - 1.5 u^2]
+// Initial state: f_a = W_a rho [1 + 3 e.u + 4.5 (e.u)^2 - 1.5 u^2], stored at
+// the unstreamed position of each distribution (state_index).
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void k_init_eq(const double* __restrict__ rho, const double* __restrict__ ux,
@@ -171,11 +241,10 @@ __global__ void k_init_eq(const double* __restrict__ rho, const double* __restri
   const int EY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
   const double W[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
                        1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
-  T* dst = f + (long long)y * geo.pitch + x;
 #pragma unroll
   for (int a = 0; a < 9; ++a) {
     const double eu = EX[a] * u + EY[a] * v;
-    dst[a * geo.plane] = T(W[a] * r * (1.0 + 3.0 * eu + 4.5 * eu * eu - uu));
+    f[state_index(geo, a, x, y)] = T(W[a] * r * (1.0 + 3.0 * eu + 4.5 * eu * eu - uu));
   }
 }
 

@@ -81,6 +81,7 @@ def load_library(path: str = LIB_PATH):
     decl = {
         "lbm_params_default": (st, [P]),
         "lbm_critical_temperature": (st, [P, dp]),
+        "lbm_coexistence": (st, [P, dp, dp]),
         "lbm_buffer_bytes": (ctypes.c_size_t, [P]),
         "lbm_create": (st, [P, vp, ctypes.POINTER(vp)]),
         "lbm_create_ext": (st, [P, vp, vp, vp, ctypes.c_size_t, ctypes.POINTER(vp)]),
@@ -131,6 +132,15 @@ def critical_temperature(cfg: dict) -> float:
     tc = ctypes.c_double()
     _check(lib.lbm_critical_temperature(ctypes.byref(p), ctypes.byref(tc)))
     return tc.value
+
+
+def coexistence(cfg: dict) -> tuple[float, float]:
+    """Maxwell (rho_v, rho_l) of the configuration's EOS at its T/Tc (host computation)."""
+    lib = load_library()
+    p = make_params(dict(cfg, nx=cfg.get("nx", 3), ny=cfg.get("ny", 3)))
+    rv, rl = ctypes.c_double(), ctypes.c_double()
+    _check(lib.lbm_coexistence(ctypes.byref(p), ctypes.byref(rv), ctypes.byref(rl)))
+    return rv.value, rl.value
 
 
 def _dptr(a: np.ndarray):

@@ -85,3 +85,20 @@ def test_library_critical_temperature_matches_oracle(lib, oracle_mod, eos):
 def test_critical_temperature_rejects_ideal(lib):
     with pytest.raises(lbm.LBMError):
         lbm.critical_temperature(dict(eos="ideal"))
+
+
+@pytest.mark.parametrize("eos,tr", [("cs", 0.8), ("cs", 0.6), ("cs", 0.85), ("cs", 0.7), ("vdw", 0.9),
+                                    ("vdw", 0.7), ("pr", 0.8), ("pr", 0.9)])
+def test_library_coexistence_matches_oracle_maxwell(lib, oracle_mod, eos, tr):
+    from oracle import thermo as th
+
+    cfg = dict(eos=eos, T_over_Tc=tr)
+    rv, rl = lbm.coexistence(cfg)
+    T, Tc = oracle_mod.temperature(cfg)
+    ov, ol = th.maxwell(oracle_mod.eos_of(cfg), T, Tc)
+    assert abs(rv / ov - 1) < 1e-9 and abs(rl / ol - 1) < 1e-9
+
+
+def test_coexistence_rejects_supercritical(lib):
+    with pytest.raises(lbm.LBMError):
+        lbm.coexistence(dict(eos="cs", T_over_Tc=1.05))

@@ -42,8 +42,15 @@ def cs_maxwell(tr):
     return th.maxwell(e, tr * Tc)
 
 
-def rel(a, b):
-    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+def rel(a, b, floor=1e-300):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), floor))
+
+
+def rel_field(k, a, b):
+    """Relative difference of a field.  Velocities are differences of O(rho) numbers
+    divided by rho, so their rounding floor is absolute (~1e-16 of the lattice speed);
+    they are measured against max(max|u|, 1e-3)."""
+    return rel(a, b, 1e-3 if k in ("ux", "uy") else 1e-300)
 
 
 def oracle_fields(o):
@@ -85,7 +92,7 @@ def test_fp64_droplet_1000_steps(lbm, oracle_mod):
     o, lat = run_pair(lbm, oracle_mod, cfg, rho0, 1000)
     og, gg = oracle_fields(o), gpu_fields(lat)
     for k in FIELDS:
-        assert rel(gg[k], og[k]) < 1e-11, (k, rel(gg[k], og[k]))
+        assert rel_field(k, gg[k], og[k]) < 1e-11, (k, rel_field(k, gg[k], og[k]))
     ob, gb = o.observables(), lat.observables()
     for k in ("mass", "rho_in", "rho_out", "rho_min", "rho_max", "p_in", "p_out", "R_e"):
         assert abs(gb[k] / ob[k] - 1) < 1e-11, k
@@ -127,7 +134,7 @@ def test_ragged_shapes_every_eos(lbm, oracle_mod, nx, ny, eos, tile, precision):
     for k in FIELDS:
         if k in ("ux", "uy") and precision == "fp32":
             continue  # velocities are differences of O(1) numbers; covered via f
-        assert rel(gg[k], og[k]) < tol, (k, rel(gg[k], og[k]))
+        assert rel_field(k, gg[k], og[k]) < tol, (k, rel_field(k, gg[k], og[k]))
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
@@ -167,14 +174,15 @@ def test_domain_clamp_matches_oracle(lbm, oracle_mod):
     """A dense blob with U > 0: psi is clamped to 0 on both sides and the cells are counted."""
     say("U>0 clamp 48x40")
     cfg = dict(nx=48, ny=40, eos="cs", T_over_Tc=0.8, A=-0.5, kappa=0.3)
-    rho0 = inputs.droplet(48, 40, 8, 0.6, 0.03, W=3.0, noise=0.0)
+    rho0 = inputs.droplet(48, 40, 8, 0.5, 0.03, W=4.0, noise=0.0)
     o, lat = run_pair(lbm, oracle_mod, cfg, rho0, 3)
     ob = o.observables()
     gb = lat.observables(check=False)
-    assert gb["status"] == -5 and gb["n_domain"] == ob["n_domain"] > 0
+    assert ob["n_nonfinite"] == 0 and ob["n_domain"] > 0
+    assert gb["status"] == -5 and gb["n_domain"] == ob["n_domain"] and gb["n_nonfinite"] == 0
     og, gg = oracle_fields(o), gpu_fields(lat)
     for k in FIELDS:
-        assert rel(gg[k], og[k]) < 1e-12, k
+        assert rel_field(k, gg[k], og[k]) < 1e-12, k
 
 
 def test_nonfinite_initial_density_rejected(lbm):
@@ -242,6 +250,10 @@ def test_full_size_4096_in_bench_launch_shape(lbm, oracle_mod, precision):
     lat = lbm.Lattice(dict(cfg, precision=precision))
     lat.init_field(rho0)
     lat.step(2)
+    # distributions are compared against the state's scale (max |f| over all planes):
+    # f_a is a sum of moments of size rho, so its rounding floor is relative to rho
+    scale = np.abs(f_ref).max()
     tol = 1e-13 if precision == "fp64" else 1e-6
     for a in range(9):
-        assert rel(lat.field(f"f{a}"), f_ref[a]) < tol, a
+        err = float(np.abs(lat.field(f"f{a}") - f_ref[a]).max() / scale)
+        assert err < tol, (a, err)
