@@ -186,6 +186,100 @@ lbm_status lbm_sync(lbm_ctx* ctx);
  * current state (for callers that time or inspect the device state). */
 lbm_status lbm_state_info(const lbm_ctx* ctx, int64_t* step, const void** f_cur, int32_t* pitch);
 
+/* ---------------------------------------------------------------------------
+ * Batched engine: n independent periodic lattices (e.g. Laplace-test droplets
+ * of uneven sizes and parameters) advanced together.  Every domain runs the
+ * same per-tile step as lbm_step.  All domains share the EOS kind and the
+ * precision; lattice size and all other parameters are per domain.
+ * ------------------------------------------------------------------------- */
+typedef struct lbm_batch lbm_batch;
+
+typedef enum {
+  LBM_BATCH_PERSISTENT = 0, /* one launch advances all domains by n steps; each domain's
+                               tiles meet at a per-domain step barrier (bounded wait) */
+  LBM_BATCH_PER_STEP = 1    /* one launch per step over all tiles, captured in HIP graphs */
+} lbm_batch_mode;
+
+typedef struct {
+  int32_t mode;             /* lbm_batch_mode                                         */
+  int32_t tile_x, tile_y;   /* tile of every domain; 0 = default (64 x 32)            */
+  int64_t spin_limit;       /* persistent mode: polls before a barrier wait gives up;
+                               0 = default (2^24)                                      */
+  int32_t force_spin_limit; /* non-zero with spin_limit 0: use 0 (test of the abort path) */
+  /* filled by lbm_batch_get_launch: */
+  int32_t grid;             /* workgroups per launch                                  */
+  int32_t ntiles;           /* tiles over all domains                                 */
+  int32_t resident_per_cu;  /* persistent mode: workgroups one CU holds at once       */
+} lbm_batch_launch;
+
+/* Creates a batch of n domains with parameters params[0..n).  Allocates one
+ * arena for all distribution buffers.  hip_stream as in lbm_create; on a
+ * non-NULL stream the steps are enqueued as HIP graphs (the persistent mode's
+ * counter reset + launch, or chunks of up to 64 per-step launches), on the
+ * null stream as plain launches.
+ * LBM_EINVAL if a domain's parameters are invalid or the EOS kinds or
+ * precisions differ. Default launch: LBM_BATCH_PER_STEP, 64 x 32 tiles. */
+lbm_status lbm_batch_create(const lbm_params* params, int32_t n, void* hip_stream, lbm_batch** out);
+void lbm_batch_destroy(lbm_batch* b);
+
+/* Chooses the launch mode and tile shape (re-plans the tiles and, in
+ * persistent mode, their assignment to a grid no larger than the GPU holds
+ * at once). */
+lbm_status lbm_batch_set_launch(lbm_batch* b, const lbm_batch_launch* launch);
+lbm_status lbm_batch_get_launch(const lbm_batch* b, lbm_batch_launch* launch);
+
+/* Initial state of domain i, as lbm_init_field (host arrays of that domain's size). */
+lbm_status lbm_batch_init_field(lbm_batch* b, int32_t i, const double* rho, const double* ux,
+                                const double* uy);
+
+/* Enqueues n steps of every domain (asynchronous).  LBM_ESTATE if a domain is
+ * not initialised. */
+lbm_status lbm_batch_step(lbm_batch* b, int64_t n);
+
+/* Waits for the batch; LBM_EDEVICE if a persistent launch aborted (a barrier
+ * wait exceeded the spin limit; the state is then not a whole step). */
+lbm_status lbm_batch_sync(lbm_batch* b);
+
+/* Observables of every domain into out[0..n) (as lbm_observables); returns the
+ * first fault status after filling all entries. */
+lbm_status lbm_batch_observables(lbm_batch* b, lbm_obs* out);
+
+/* One field of domain i, as lbm_get_field. */
+lbm_status lbm_batch_get_field(lbm_batch* b, int32_t i, int32_t which, double* out);
+
+/* ---------------------------------------------------------------------------
+ * Surrogate network: (A, kappa, T/Tc) -> (sigma, rho_l, rho_v), each
+ * normalised by the caller.  3 -> 128 -> 128 -> 128 -> 3, tanh on the hidden
+ * layers, linear output; 33,923 parameters in one flat FP32 vector in the
+ * order W1 [128x3], b1, W2 [128x128], b2, W3 [128x128], b3, W4 [3x128], b4
+ * (W is [out, in], row-major).  The weights are used rounded to bfloat16
+ * (nearest, ties to even) from the FP32 master copy; biases, activations and
+ * accumulation are FP32.  Training is full-batch Adam (beta1 0.9, beta2
+ * 0.999, eps 1e-8) on the mean squared error over the 3 outputs.  Host
+ * arrays are float, n x 3, row-major.
+ * ------------------------------------------------------------------------- */
+typedef struct lbm_mlp lbm_mlp;
+
+int32_t lbm_mlp_param_count(void);
+/* max_batch: largest n of any later call (<= 2^20).  Parameters start at 0. */
+lbm_status lbm_mlp_create(int32_t max_batch, void* hip_stream, lbm_mlp** out);
+void lbm_mlp_destroy(lbm_mlp* m);
+/* Sets the FP32 master parameters (and their bfloat16 copy); resets Adam. */
+lbm_status lbm_mlp_set_params(lbm_mlp* m, const float* params);
+lbm_status lbm_mlp_get_params(lbm_mlp* m, float* params);
+/* y[n x 3] = network(x[n x 3]). */
+lbm_status lbm_mlp_forward(lbm_mlp* m, const float* x, int32_t n, float* y);
+/* Gradients of sum(dy * y) with respect to the parameters (grad, 33,923
+ * values; weight entries with respect to the rounded weights) and to the
+ * inputs (dx, n x 3).  Either output may be NULL. */
+lbm_status lbm_mlp_backward(lbm_mlp* m, const float* x, const float* dy, int32_t n, float* grad,
+                            float* dx);
+/* Training set (n <= max_batch) kept on the device. */
+lbm_status lbm_mlp_set_data(lbm_mlp* m, const float* x, const float* t, int32_t n);
+/* iters full-batch Adam steps with learning rate lr; loss_out (iters values,
+ * may be NULL) receives the loss before each step. */
+lbm_status lbm_mlp_train(lbm_mlp* m, int32_t iters, float lr, float* loss_out);
+
 const char* lbm_strerror(lbm_status s);
 /* Message of the last error on the calling thread ("" if none). */
 const char* lbm_last_error(void);

@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "lbm_internal.h"
 
@@ -231,6 +232,24 @@ lbm_status coexistence(const lbm_params& p, double* rv, double* rl) {
   return LBM_OK;
 }
 
+lbm_status model_of(const lbm_params& p, ModelConsts* m) {
+  m->eos = p.eos;
+  m->K = p.K; m->R = p.R; m->a = p.a; m->b = p.b;
+  m->G = p.eos == LBM_EOS_IDEAL ? -1.0 : p.G;
+  m->A = p.A; m->kappa = p.kappa;
+  m->s_e = p.s_e; m->s_eps = p.s_eps; m->s_q = p.s_q; m->s_nu = p.s_nu;
+  m->T = 0.0;
+  m->aalpha = p.a;
+  if (p.eos != LBM_EOS_IDEAL) {
+    double Tc = 0.0;
+    lbm_status st = critical_temperature(p, &Tc);
+    if (st != LBM_OK) return st;
+    m->T = p.T_over_Tc * Tc;
+    if (p.eos == LBM_EOS_PR) m->aalpha = p.a * pr_alpha(p.omega_pr, p.T_over_Tc);
+  }
+  return LBM_OK;
+}
+
 lbm_status validate(const lbm_params* p) {
   if (!p) return fail(LBM_EINVAL, "params is NULL");
   if (p->nx < 3 || p->ny < 3) return fail(LBM_EINVAL, "lattice %d x %d: each side must be >= 3", p->nx, p->ny);
@@ -304,15 +323,20 @@ void set_geometry(lbm_ctx* c, int tile_x, int tile_y) {
 }
 
 // Default launch shape: strips as wide as the lattice allows (up to 256
-// columns), row blocks sized so that the grid holds about 2048 workgroups
-// (8 per CU), never fewer than 16 rows.
+// columns); rows per workgroup a power of two from 64 down to 8, the largest
+// that still gives at least 4 workgroups per CU.  (Measured on the 4096^2
+// lattice: 64 and 16 rows are equally fast; grids that are not a multiple of
+// the CU count leave some CUs a block more than others.)
 void default_launch(const lbm_params& p, int* tx, int* ty) {
   *tx = p.nx >= 256 ? 256 : (p.nx >= 128 ? 128 : 64);
-  const int strips = (p.nx + *tx - 1) / *tx;
-  const int want_rb = std::max(1, 2048 / strips);
-  int rows = (p.ny + want_rb - 1) / want_rb;
-  rows = std::max(rows, std::min(16, p.ny));
-  *ty = rows;
+  int cus = 0, dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+    cus = 256;
+  const long long strips = (p.nx + *tx - 1) / *tx;
+  int rows = 64;
+  while (rows > 8 && strips * ((p.ny + rows - 1) / rows) < 4ll * cus) rows /= 2;
+  *ty = std::min(rows, p.ny);
 }
 
 lbm_status ensure_scratch(lbm_ctx* c) {
@@ -333,21 +357,8 @@ lbm_status make_ctx(const lbm_params* p, void* stream, void* ba, void* bb, size_
   lbm_ctx* c = new (std::nothrow) lbm_ctx();
   if (!c) return fail(LBM_ENOMEM, "host allocation failed");
   c->p = *p;
-  ModelConsts& m = c->m;
-  m.eos = p->eos;
-  m.K = p->K; m.R = p->R; m.a = p->a; m.b = p->b;
-  m.G = p->eos == LBM_EOS_IDEAL ? -1.0 : p->G;
-  m.A = p->A; m.kappa = p->kappa;
-  m.s_e = p->s_e; m.s_eps = p->s_eps; m.s_q = p->s_q; m.s_nu = p->s_nu;
-  m.T = 0.0;
-  m.aalpha = p->a;
-  if (p->eos != LBM_EOS_IDEAL) {
-    double Tc = 0.0;
-    st = critical_temperature(*p, &Tc);
-    if (st != LBM_OK) { delete c; return st; }
-    m.T = p->T_over_Tc * Tc;
-    if (p->eos == LBM_EOS_PR) m.aalpha = p->a * pr_alpha(p->omega_pr, p->T_over_Tc);
-  }
+  st = model_of(*p, &c->m);
+  if (st != LBM_OK) { delete c; return st; }
   int tx, ty;
   default_launch(*p, &tx, &ty);
   set_geometry(c, tx, ty);
@@ -385,6 +396,70 @@ lbm_status make_ctx(const lbm_params* p, void* stream, void* ba, void* bb, size_
 
 lbm_status copy_to_device(lbm_ctx* c, double* dst, const double* src, size_t n) {
   HIP_TRY(hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  return LBM_OK;
+}
+
+lbm_status check_density(const double* rho, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!(rho[i] > 0.0) || !std::isfinite(rho[i]))
+      return fail(LBM_ENONFINITE, "initial density %g at cell %zu", rho[i], i);
+  return LBM_OK;
+}
+
+// FP64 observables of one state (shared by lattices and batch domains).
+lbm_status observe(const lbm_params& p, const ModelConsts& m, const Geometry& g, const void* f,
+                   int64_t step, double* work, double* partials, double* red, hipStream_t stream,
+                   lbm_obs* o) {
+  const lbm_precision prec = (lbm_precision)p.precision;
+  HIP_TRY(launch_density_fields(prec, g, m, f, work, stream));
+  HIP_TRY(launch_observables(prec, g, m, f, work, partials, red, stream));
+  const size_t n = (size_t)p.nx * p.ny;
+  const size_t i_in = (size_t)(p.ny / 2) * p.nx + p.nx / 2;
+  HIP_TRY(hipMemcpyAsync(red + kNumRed, work + i_in, sizeof(double), hipMemcpyDeviceToDevice, stream));
+  HIP_TRY(hipMemcpyAsync(red + kNumRed + 1, work, sizeof(double), hipMemcpyDeviceToDevice, stream));
+  double h[kNumRed + 2];
+  HIP_TRY(hipMemcpyAsync(h, red, sizeof h, hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  o->step = step;
+  o->mass = h[0];
+  o->mom_x = h[1];
+  o->mom_y = h[2];
+  o->rho_min = h[3];
+  o->rho_max = h[4];
+  o->max_u = std::sqrt(h[5]);
+  o->n_domain = (int64_t)h[6];
+  o->n_nonfinite = (int64_t)h[7];
+  o->rho_in = h[kNumRed];
+  o->rho_out = h[kNumRed + 1];
+  o->p_in = eos_pressure(p.eos, m.aalpha, p.b, p.R, p.K, m.T, p.a, o->rho_in);
+  o->p_out = eos_pressure(p.eos, m.aalpha, p.b, p.R, p.K, m.T, p.a, o->rho_out);
+  o->dp = o->p_in - o->p_out;
+  const double excess = o->mass - (double)n * o->rho_out;
+  o->R_e = std::sqrt(excess / (o->rho_in - o->rho_out) / M_PI);
+  o->sigma = o->dp * o->R_e;
+  if (o->n_nonfinite > 0) return fail(LBM_ENONFINITE, "%lld cells with non-finite or non-positive density", (long long)o->n_nonfinite);
+  if (o->n_domain > 0) return fail(LBM_EDOMAIN, "%lld cells with U > 0", (long long)o->n_domain);
+  return LBM_OK;
+}
+
+lbm_status read_field(const lbm_params& p, const ModelConsts& m, const Geometry& g, const void* f,
+                      int32_t which, double* work, hipStream_t stream, double* out) {
+  if (which < LBM_FIELD_RHO || which > LBM_FIELD_F0 + 8) return fail(LBM_EINVAL, "unknown field %d", which);
+  const lbm_precision prec = (lbm_precision)p.precision;
+  const size_t n = (size_t)p.nx * p.ny;
+  double* src = work;
+  if (which >= LBM_FIELD_F0) {
+    src = work + 3 * n;
+    HIP_TRY(launch_plane_to_f64(prec, g, f, which - LBM_FIELD_F0, src, stream));
+  } else {
+    HIP_TRY(launch_density_fields(prec, g, m, f, work, stream));
+    if (which != LBM_FIELD_RHO) {
+      src = work + 3 * n;
+      HIP_TRY(launch_velocity_field(prec, g, m, f, work, which == LBM_FIELD_UX ? 0 : 1, src, stream));
+    }
+  }
+  HIP_TRY(hipMemcpyAsync(out, src, n * sizeof(double), hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
   return LBM_OK;
 }
 
@@ -471,10 +546,9 @@ lbm_status lbm_get_launch(const lbm_ctx* c, lbm_launch* l) {
 lbm_status lbm_init_field(lbm_ctx* c, const double* rho, const double* ux, const double* uy) {
   if (!c || !rho) return fail(LBM_EINVAL, "NULL argument");
   const size_t n = (size_t)c->p.nx * c->p.ny;
-  for (size_t i = 0; i < n; ++i)
-    if (!(rho[i] > 0.0) || !std::isfinite(rho[i]))
-      return fail(LBM_ENONFINITE, "initial density %g at cell %zu", rho[i], i);
-  lbm_status st = ensure_scratch(c);
+  lbm_status st = check_density(rho, n);
+  if (st != LBM_OK) return st;
+  st = ensure_scratch(c);
   if (st != LBM_OK) return st;
   double* d_rho = c->work;
   double* d_ux = ux ? c->work + n : nullptr;
@@ -526,64 +600,15 @@ lbm_status lbm_observables(lbm_ctx* c, lbm_obs* o) {
   if (!c->initialized) return fail(LBM_ESTATE, "observables before lbm_init_field");
   lbm_status st = ensure_scratch(c);
   if (st != LBM_OK) return st;
-  const lbm_precision prec = (lbm_precision)c->p.precision;
-  const void* f = c->buf[c->cur];
-  HIP_TRY(launch_density_fields(prec, c->g, c->m, f, c->work, c->stream));
-  HIP_TRY(launch_observables(prec, c->g, c->m, f, c->work, c->partials, c->red, c->stream));
-  const size_t n = (size_t)c->p.nx * c->p.ny;
-  const size_t i_in = (size_t)(c->p.ny / 2) * c->p.nx + c->p.nx / 2;
-  HIP_TRY(hipMemcpyAsync(c->red + kNumRed, c->work + i_in, sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-  HIP_TRY(hipMemcpyAsync(c->red + kNumRed + 1, c->work, sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-  double h[kNumRed + 2];
-  HIP_TRY(hipMemcpyAsync(h, c->red, sizeof h, hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(hipStreamSynchronize(c->stream));
-  const lbm_params& p = c->p;
-  const ModelConsts& m = c->m;
-  o->step = c->step;
-  o->mass = h[0];
-  o->mom_x = h[1];
-  o->mom_y = h[2];
-  o->rho_min = h[3];
-  o->rho_max = h[4];
-  o->max_u = std::sqrt(h[5]);
-  o->n_domain = (int64_t)h[6];
-  o->n_nonfinite = (int64_t)h[7];
-  o->rho_in = h[kNumRed];
-  o->rho_out = h[kNumRed + 1];
-  o->p_in = eos_pressure(p.eos, m.aalpha, p.b, p.R, p.K, m.T, p.a, o->rho_in);
-  o->p_out = eos_pressure(p.eos, m.aalpha, p.b, p.R, p.K, m.T, p.a, o->rho_out);
-  o->dp = o->p_in - o->p_out;
-  const double excess = o->mass - (double)n * o->rho_out;
-  o->R_e = std::sqrt(excess / (o->rho_in - o->rho_out) / M_PI);
-  o->sigma = o->dp * o->R_e;
-  if (o->n_nonfinite > 0) return fail(LBM_ENONFINITE, "%lld cells with non-finite or non-positive density", (long long)o->n_nonfinite);
-  if (o->n_domain > 0) return fail(LBM_EDOMAIN, "%lld cells with U > 0", (long long)o->n_domain);
-  return LBM_OK;
+  return observe(c->p, c->m, c->g, c->buf[c->cur], c->step, c->work, c->partials, c->red, c->stream, o);
 }
 
 lbm_status lbm_get_field(lbm_ctx* c, int32_t which, double* out) {
   if (!c || !out) return fail(LBM_EINVAL, "NULL argument");
-  if (which < LBM_FIELD_RHO || which > LBM_FIELD_F0 + 8) return fail(LBM_EINVAL, "unknown field %d", which);
   if (!c->initialized) return fail(LBM_ESTATE, "field before lbm_init_field");
   lbm_status st = ensure_scratch(c);
   if (st != LBM_OK) return st;
-  const lbm_precision prec = (lbm_precision)c->p.precision;
-  const size_t n = (size_t)c->p.nx * c->p.ny;
-  const void* f = c->buf[c->cur];
-  double* src = c->work;
-  if (which >= LBM_FIELD_F0) {
-    src = c->work + 3 * n;
-    HIP_TRY(launch_plane_to_f64(prec, c->g, f, which - LBM_FIELD_F0, src, c->stream));
-  } else {
-    HIP_TRY(launch_density_fields(prec, c->g, c->m, f, c->work, c->stream));
-    if (which != LBM_FIELD_RHO) {
-      src = c->work + 3 * n;
-      HIP_TRY(launch_velocity_field(prec, c->g, c->m, f, c->work, which == LBM_FIELD_UX ? 0 : 1, src, c->stream));
-    }
-  }
-  HIP_TRY(hipMemcpyAsync(out, src, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(hipStreamSynchronize(c->stream));
-  return LBM_OK;
+  return read_field(c->p, c->m, c->g, c->buf[c->cur], which, c->work, c->stream, out);
 }
 
 lbm_status lbm_save_state(lbm_ctx* c, void* buf, size_t* len) {
@@ -649,5 +674,537 @@ const char* lbm_strerror(lbm_status s) {
 }
 
 const char* lbm_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"
+
+// ===========================================================================
+// Batched engine (host side)
+// ===========================================================================
+struct lbm_batch {
+  int n = 0;
+  std::vector<lbm_params> p;
+  std::vector<ModelConsts> m;
+  std::vector<Geometry> g;
+  std::vector<size_t> off[2];
+  std::vector<unsigned> ntiles;
+  std::vector<bool> inited;
+  lbm_precision prec = LBM_FP64;
+  int eos = 0;
+  void* arena = nullptr;
+  size_t arena_bytes = 0;
+  hipStream_t stream = nullptr;
+  int mode = LBM_BATCH_PER_STEP;
+  int tile_x = 64, tile_y = 32;
+  long long spin_limit = 1ll << 24;
+  int per_cu = 0, cus = 0;
+  // device layout
+  void* d_dom = nullptr;
+  void* d_tiles = nullptr;
+  int* d_wg_begin = nullptr;
+  unsigned* d_done = nullptr;
+  int* d_err = nullptr;
+  int ntile_total = 0, grid = 0;
+  // state
+  int parity = 0;
+  int64_t step = 0;
+  // graph cache
+  hipGraphExec_t exec = nullptr;
+  int exec_mode = -1, exec_steps = 0, exec_parity = -1;
+  // FP64 scratch for observables / fields
+  double* work = nullptr;
+  double* partials = nullptr;
+  double* red = nullptr;
+};
+
+namespace {
+
+void batch_free_layout(lbm_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  b->exec = nullptr;
+  b->exec_mode = -1;
+  for (void* q : {b->d_dom, b->d_tiles, (void*)b->d_wg_begin})
+    if (q) (void)hipFree(q);
+  b->d_dom = b->d_tiles = nullptr;
+  b->d_wg_begin = nullptr;
+}
+
+// Tiles of every domain, the workgroup assignment (persistent mode: longest
+// processing time first onto the least loaded workgroup) and the device copies.
+lbm_status batch_layout(lbm_batch* b) {
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  batch_free_layout(b);
+  HIP_TRY(hipMemsetAsync(b->d_err, 0, sizeof(int), b->stream));
+  struct T4 { int d, x0, y0, down; long long cost; };
+  std::vector<T4> tiles;
+  b->ntiles.assign(b->n, 0);
+  for (int d = 0; d < b->n; ++d) {
+    Geometry& g = b->g[d];
+    g.tile_x = b->tile_x;
+    g.tile_y = std::min(b->tile_y, g.ny);
+    g.nstrips = (g.nx + g.tile_x - 1) / g.tile_x;
+    g.nrowblocks = (g.ny + g.tile_y - 1) / g.tile_y;
+    g.nblocks = g.nstrips * g.nrowblocks;
+    for (int rb = 0; rb < g.nrowblocks; ++rb)
+      for (int sx = 0; sx < g.nstrips; ++sx) {
+        const int x0 = sx * g.tile_x, y0 = rb * g.tile_y;
+        const long long w = std::min(g.tile_x, g.nx - x0), h = std::min(g.tile_y, g.ny - y0);
+        tiles.push_back({d, x0, y0, rb & 1, w * (h + 2)});
+      }
+    b->ntiles[d] = (unsigned)g.nblocks;
+  }
+  b->ntile_total = (int)tiles.size();
+  std::vector<int> wg_begin;
+  if (b->mode == LBM_BATCH_PERSISTENT) {
+    HIP_TRY(batch_occupancy(b->prec, b->eos, b->tile_x, &b->per_cu));
+    if (b->per_cu < 1) return fail(LBM_EDEVICE, "persistent batch kernel cannot be resident");
+    b->grid = std::min(b->ntile_total, b->per_cu * b->cus);
+    std::vector<int> order(tiles.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return tiles[a].cost > tiles[c].cost; });
+    // min-heap of (load, workgroup)
+    std::vector<std::pair<long long, int>> heap;
+    for (int w = 0; w < b->grid; ++w) heap.push_back({0, w});
+    std::vector<std::vector<int>> own(b->grid);
+    auto cmp = [](const std::pair<long long, int>& a, const std::pair<long long, int>& c) {
+      return a.first > c.first || (a.first == c.first && a.second > c.second);
+    };
+    std::make_heap(heap.begin(), heap.end(), cmp);
+    for (int t : order) {
+      std::pop_heap(heap.begin(), heap.end(), cmp);
+      auto& top = heap.back();
+      own[top.second].push_back(t);
+      top.first += tiles[t].cost;
+      std::push_heap(heap.begin(), heap.end(), cmp);
+    }
+    std::vector<T4> sorted;
+    wg_begin.push_back(0);
+    for (int w = 0; w < b->grid; ++w) {
+      std::sort(own[w].begin(), own[w].end());  // domain, then row block, then strip order
+      for (int t : own[w]) sorted.push_back(tiles[t]);
+      wg_begin.push_back((int)sorted.size());
+    }
+    tiles.swap(sorted);
+  } else {
+    b->grid = b->ntile_total;
+    wg_begin.assign(2, 0);
+  }
+  const size_t db = batch_domain_bytes(b->prec), tb = batch_tile_bytes();
+  std::vector<unsigned char> hd(db * b->n), ht(tb * tiles.size());
+  for (int d = 0; d < b->n; ++d)
+    batch_fill_domain(b->prec, b->g[d], b->m[d], static_cast<char*>(b->arena) + b->off[0][d],
+                      static_cast<char*>(b->arena) + b->off[1][d], b->ntiles[d], hd.data() + d * db);
+  for (size_t t = 0; t < tiles.size(); ++t)
+    batch_fill_tile(tiles[t].d, tiles[t].x0, tiles[t].y0, tiles[t].down, ht.data() + t * tb);
+  HIP_TRY(hipMalloc(&b->d_dom, hd.size()));
+  HIP_TRY(hipMalloc(&b->d_tiles, ht.size()));
+  HIP_TRY(hipMalloc(&b->d_wg_begin, wg_begin.size() * sizeof(int)));
+  HIP_TRY(hipMemcpyAsync(b->d_dom, hd.data(), hd.size(), hipMemcpyHostToDevice, b->stream));
+  HIP_TRY(hipMemcpyAsync(b->d_tiles, ht.data(), ht.size(), hipMemcpyHostToDevice, b->stream));
+  HIP_TRY(hipMemcpyAsync(b->d_wg_begin, wg_begin.data(), wg_begin.size() * sizeof(int),
+                         hipMemcpyHostToDevice, b->stream));
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  return LBM_OK;
+}
+
+// Enqueue `n` steps as one graph: persistent = counter reset + one launch;
+// per-step = n launches with alternating buffers.
+lbm_status batch_graph(lbm_batch* b, int n) {
+  if (b->exec && b->exec_mode == b->mode && b->exec_steps == n && b->exec_parity == b->parity)
+    return LBM_OK;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  b->exec = nullptr;
+  hipGraph_t graph = nullptr;
+  HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+  hipError_t e = hipSuccess;
+  if (b->mode == LBM_BATCH_PERSISTENT) {
+    e = launch_batch_reset(b->d_done, b->n, b->d_err, b->stream);
+    if (e == hipSuccess)
+      e = launch_batch(b->prec, b->eos, b->tile_x, true, b->d_dom, b->d_tiles, b->d_wg_begin,
+                       b->d_done, b->d_err, b->grid, n, b->parity, b->spin_limit, b->stream);
+  } else {
+    for (int s = 0; s < n && e == hipSuccess; ++s)
+      e = launch_batch(b->prec, b->eos, b->tile_x, false, b->d_dom, b->d_tiles, nullptr, nullptr,
+                       nullptr, b->grid, 1, (b->parity + s) & 1, 0, b->stream);
+  }
+  hipError_t e2 = hipStreamEndCapture(b->stream, &graph);
+  if (e != hipSuccess || e2 != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return fail(LBM_EDEVICE, "batch graph capture: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+  }
+  e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return fail(LBM_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  b->exec_mode = b->mode;
+  b->exec_steps = n;
+  b->exec_parity = b->parity;
+  return LBM_OK;
+}
+
+lbm_status batch_scratch(lbm_batch* b) {
+  if (b->work) return LBM_OK;
+  size_t cells = 0;
+  int parts = 0;
+  for (int d = 0; d < b->n; ++d) {
+    cells = std::max(cells, (size_t)b->p[d].nx * b->p[d].ny);
+    parts = std::max(parts, obs_partials_count(b->g[d]));
+  }
+  HIP_TRY(hipMalloc(&b->work, 4 * cells * sizeof(double)));
+  HIP_TRY(hipMalloc(&b->partials, (size_t)parts * kNumRed * sizeof(double)));
+  HIP_TRY(hipMalloc(&b->red, (kNumRed + 2) * sizeof(double)));
+  return LBM_OK;
+}
+
+lbm_status batch_check_error(lbm_batch* b) {
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  int err = 0;
+  HIP_TRY(hipMemcpy(&err, b->d_err, sizeof err, hipMemcpyDeviceToHost));
+  if (err) {
+    // reported once; the state of an aborted launch is not a whole step
+    HIP_TRY(hipMemsetAsync(b->d_err, 0, sizeof(int), b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    return fail(LBM_EDEVICE, "persistent batch launch aborted: a domain barrier wait exceeded the spin limit");
+  }
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_batch_create(const lbm_params* params, int32_t n, void* hip_stream, lbm_batch** out) {
+  if (!params || !out || n < 1) return fail(LBM_EINVAL, "batch: NULL argument or n < 1");
+  *out = nullptr;
+  for (int i = 0; i < n; ++i) {
+    lbm_status st = validate(&params[i]);
+    if (st != LBM_OK) return fail(st, "batch domain %d: %s", i, g_last_error.c_str());
+    if (params[i].eos != params[0].eos || params[i].precision != params[0].precision)
+      return fail(LBM_EINVAL, "batch domain %d: every domain must share the EOS kind and precision", i);
+  }
+  lbm_batch* b = new (std::nothrow) lbm_batch();
+  if (!b) return fail(LBM_ENOMEM, "host allocation failed");
+  b->n = n;
+  b->prec = (lbm_precision)params[0].precision;
+  b->eos = params[0].eos;
+  b->stream = static_cast<hipStream_t>(hip_stream);
+  b->p.assign(params, params + n);
+  b->m.resize(n);
+  b->g.resize(n);
+  b->off[0].resize(n);
+  b->off[1].resize(n);
+  b->inited.assign(n, false);
+  const size_t es = elem_size(params[0]);
+  size_t total = 0;
+  for (int d = 0; d < n; ++d) {
+    lbm_status st = model_of(params[d], &b->m[d]);
+    if (st != LBM_OK) { lbm_batch_destroy(b); return st; }
+    Geometry& g = b->g[d];
+    g.nx = params[d].nx;
+    g.ny = params[d].ny;
+    g.pitch = pitch_of(params[d]);
+    g.plane = (long long)g.ny * g.pitch;
+    const size_t bytes = (9 * (size_t)g.plane * es + 255) / 256 * 256;
+    if (9 * (size_t)g.plane * es >= (1ull << 32)) {
+      lbm_batch_destroy(b);
+      return fail(LBM_EINVAL, "batch domain %d: a distribution buffer must stay below 4 GiB", d);
+    }
+    b->off[0][d] = total;
+    b->off[1][d] = total + bytes;
+    total += 2 * bytes;
+  }
+  b->arena_bytes = total;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipMalloc(&b->arena, total);
+  if (e == hipSuccess) e = hipMemsetAsync(b->arena, 0, total, b->stream);
+  if (e == hipSuccess) e = hipMalloc(&b->d_done, n * sizeof(unsigned));
+  if (e == hipSuccess) e = hipMalloc(&b->d_err, sizeof(int));
+  if (e == hipSuccess) e = hipMemsetAsync(b->d_err, 0, sizeof(int), b->stream);
+  if (e != hipSuccess) {
+    lbm_batch_destroy(b);
+    return fail(e == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE, "batch allocation: %s", hipGetErrorString(e));
+  }
+  lbm_status st = batch_layout(b);
+  if (st != LBM_OK) { lbm_batch_destroy(b); return st; }
+  *out = b;
+  return LBM_OK;
+}
+
+void lbm_batch_destroy(lbm_batch* b) {
+  if (!b) return;
+  (void)hipStreamSynchronize(b->stream);
+  batch_free_layout(b);
+  for (void* q : {b->arena, (void*)b->d_done, (void*)b->d_err, (void*)b->work, (void*)b->partials, (void*)b->red})
+    if (q) (void)hipFree(q);
+  delete b;
+}
+
+lbm_status lbm_batch_set_launch(lbm_batch* b, const lbm_batch_launch* l) {
+  if (!b || !l) return fail(LBM_EINVAL, "NULL argument");
+  if (l->mode != LBM_BATCH_PERSISTENT && l->mode != LBM_BATCH_PER_STEP)
+    return fail(LBM_EINVAL, "unknown batch mode %d", l->mode);
+  const int tx = l->tile_x ? l->tile_x : 64, ty = l->tile_y ? l->tile_y : 32;
+  if (tx != 64 && tx != 128 && tx != 256) return fail(LBM_EINVAL, "tile_x %d not in {64,128,256}", tx);
+  if (ty < 1) return fail(LBM_EINVAL, "tile_y %d < 1", ty);
+  if (l->spin_limit < 0) return fail(LBM_EINVAL, "negative spin limit");
+  b->mode = l->mode;
+  b->tile_x = tx;
+  b->tile_y = ty;
+  b->spin_limit = l->spin_limit ? l->spin_limit : (1ll << 24);
+  if (l->spin_limit == 0 && l->force_spin_limit) b->spin_limit = 0;
+  return batch_layout(b);
+}
+
+lbm_status lbm_batch_get_launch(const lbm_batch* b, lbm_batch_launch* l) {
+  if (!b || !l) return fail(LBM_EINVAL, "NULL argument");
+  l->mode = b->mode;
+  l->tile_x = b->tile_x;
+  l->tile_y = b->tile_y;
+  l->spin_limit = b->spin_limit;
+  l->force_spin_limit = 0;
+  l->grid = b->grid;
+  l->ntiles = b->ntile_total;
+  l->resident_per_cu = b->per_cu;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_init_field(lbm_batch* b, int32_t i, const double* rho, const double* ux,
+                                const double* uy) {
+  if (!b || !rho) return fail(LBM_EINVAL, "NULL argument");
+  if (i < 0 || i >= b->n) return fail(LBM_EINVAL, "domain %d out of range", i);
+  const size_t n = (size_t)b->p[i].nx * b->p[i].ny;
+  lbm_status st = check_density(rho, n);
+  if (st != LBM_OK) return st;
+  if ((st = batch_scratch(b)) != LBM_OK) return st;
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  HIP_TRY(hipMemcpyAsync(b->work, rho, n * sizeof(double), hipMemcpyHostToDevice, b->stream));
+  if (ux) HIP_TRY(hipMemcpyAsync(b->work + n, ux, n * sizeof(double), hipMemcpyHostToDevice, b->stream));
+  if (uy) HIP_TRY(hipMemcpyAsync(b->work + 2 * n, uy, n * sizeof(double), hipMemcpyHostToDevice, b->stream));
+  void* f = static_cast<char*>(b->arena) + b->off[b->parity][i];
+  HIP_TRY(launch_init_equilibrium(b->prec, b->g[i], b->work, ux ? b->work + n : nullptr,
+                                  uy ? b->work + 2 * n : nullptr, f, b->stream));
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  b->inited[i] = true;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_step(lbm_batch* b, int64_t n) {
+  if (!b) return fail(LBM_EINVAL, "NULL batch");
+  if (n < 0) return fail(LBM_EINVAL, "negative step count");
+  for (int d = 0; d < b->n; ++d)
+    if (!b->inited[d]) return fail(LBM_ESTATE, "batch domain %d not initialised", d);
+  // persistent mode: the whole call is one launch (chunked only beyond 2^30
+  // steps); per-step mode: graphs of up to 64 launches
+  const int64_t chunk = b->mode == LBM_BATCH_PERSISTENT ? (1ll << 30) : 64;
+  int64_t left = n;
+  while (left > 0) {
+    const int k = (int)std::min(left, chunk);
+    if (b->stream) {
+      // graphs cannot be captured on the legacy null stream: only on a real stream
+      lbm_status st = batch_graph(b, k);
+      if (st != LBM_OK) return st;
+      HIP_TRY(hipGraphLaunch(b->exec, b->stream));
+    } else if (b->mode == LBM_BATCH_PERSISTENT) {
+      HIP_TRY(launch_batch_reset(b->d_done, b->n, b->d_err, b->stream));
+      HIP_TRY(launch_batch(b->prec, b->eos, b->tile_x, true, b->d_dom, b->d_tiles, b->d_wg_begin,
+                           b->d_done, b->d_err, b->grid, k, b->parity, b->spin_limit, b->stream));
+    } else {
+      for (int s2 = 0; s2 < k; ++s2)
+        HIP_TRY(launch_batch(b->prec, b->eos, b->tile_x, false, b->d_dom, b->d_tiles, nullptr,
+                             nullptr, nullptr, b->grid, 1, (b->parity + s2) & 1, 0, b->stream));
+    }
+    b->parity = (b->parity + k) & 1;
+    left -= k;
+  }
+  b->step += n;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_sync(lbm_batch* b) {
+  if (!b) return fail(LBM_EINVAL, "NULL batch");
+  return batch_check_error(b);
+}
+
+lbm_status lbm_batch_observables(lbm_batch* b, lbm_obs* out) {
+  if (!b || !out) return fail(LBM_EINVAL, "NULL argument");
+  lbm_status st = batch_check_error(b);
+  if (st != LBM_OK) return st;
+  if ((st = batch_scratch(b)) != LBM_OK) return st;
+  lbm_status worst = LBM_OK;
+  for (int d = 0; d < b->n; ++d) {
+    const void* f = static_cast<char*>(b->arena) + b->off[b->parity][d];
+    st = observe(b->p[d], b->m[d], b->g[d], f, b->step, b->work, b->partials, b->red, b->stream, &out[d]);
+    if (st == LBM_EDEVICE || st == LBM_ENOMEM) return st;
+    if (st != LBM_OK && worst == LBM_OK) worst = st;
+  }
+  if (worst != LBM_OK) return fail(worst, "at least one batch domain holds non-finite densities or U > 0 cells");
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_get_field(lbm_batch* b, int32_t i, int32_t which, double* out) {
+  if (!b || !out) return fail(LBM_EINVAL, "NULL argument");
+  if (i < 0 || i >= b->n) return fail(LBM_EINVAL, "domain %d out of range", i);
+  lbm_status st = batch_check_error(b);
+  if (st != LBM_OK) return st;
+  if ((st = batch_scratch(b)) != LBM_OK) return st;
+  const void* f = static_cast<char*>(b->arena) + b->off[b->parity][i];
+  return read_field(b->p[i], b->m[i], b->g[i], f, which, b->work, b->stream, out);
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Surrogate network (host side)
+// ===========================================================================
+struct lbm_mlp {
+  int max_batch = 0;
+  hipStream_t stream = nullptr;
+  float *p = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr, *gpart = nullptr;
+  unsigned short* wb = nullptr;
+  float *x = nullptr, *t = nullptr, *y = nullptr, *dy = nullptr, *acts = nullptr, *dx = nullptr;
+  float* loss = nullptr;
+  int loss_cap = 0;
+  int ndata = 0;
+  int64_t adam_t = 0;
+};
+
+namespace {
+
+lbm_status mlp_check_n(const lbm_mlp* m, int32_t n) {
+  if (n < 1 || n > m->max_batch) return fail(LBM_EINVAL, "batch of %d samples outside [1, %d]", n, m->max_batch);
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t lbm_mlp_param_count(void) { return mlp_param_count(); }
+
+lbm_status lbm_mlp_create(int32_t max_batch, void* hip_stream, lbm_mlp** out) {
+  if (!out || max_batch < 1 || max_batch > (1 << 20)) return fail(LBM_EINVAL, "max_batch must be in [1, 2^20]");
+  *out = nullptr;
+  lbm_mlp* m = new (std::nothrow) lbm_mlp();
+  if (!m) return fail(LBM_ENOMEM, "host allocation failed");
+  m->max_batch = max_batch;
+  m->stream = static_cast<hipStream_t>(hip_stream);
+  const size_t np = mlp_param_count();
+  const int nwg = (max_batch + mlp_rows_per_block() - 1) / mlp_rows_per_block();
+  hipError_t e = hipSuccess;
+  auto alloc = [&](void** q, size_t bytes) { if (e == hipSuccess) e = hipMalloc(q, bytes); };
+  alloc((void**)&m->p, np * 4);
+  alloc((void**)&m->m, np * 4);
+  alloc((void**)&m->v, np * 4);
+  alloc((void**)&m->grad, np * 4);
+  alloc((void**)&m->gpart, (size_t)nwg * np * 4);
+  alloc((void**)&m->wb, np * 2);
+  alloc((void**)&m->x, (size_t)max_batch * 3 * 4);
+  alloc((void**)&m->t, (size_t)max_batch * 3 * 4);
+  alloc((void**)&m->y, (size_t)max_batch * 3 * 4);
+  alloc((void**)&m->dy, (size_t)max_batch * 3 * 4);
+  alloc((void**)&m->dx, (size_t)max_batch * 3 * 4);
+  alloc((void**)&m->acts, (size_t)max_batch * 3 * 128 * 4);
+  if (e == hipSuccess) e = hipMemsetAsync(m->p, 0, np * 4, m->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(m->m, 0, np * 4, m->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(m->v, 0, np * 4, m->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(m->wb, 0, np * 2, m->stream);
+  if (e != hipSuccess) {
+    lbm_mlp_destroy(m);
+    return fail(e == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE, "mlp allocation: %s", hipGetErrorString(e));
+  }
+  *out = m;
+  return LBM_OK;
+}
+
+void lbm_mlp_destroy(lbm_mlp* m) {
+  if (!m) return;
+  (void)hipStreamSynchronize(m->stream);
+  for (void* q : {(void*)m->p, (void*)m->m, (void*)m->v, (void*)m->grad, (void*)m->gpart, (void*)m->wb,
+                  (void*)m->x, (void*)m->t, (void*)m->y, (void*)m->dy, (void*)m->dx, (void*)m->acts,
+                  (void*)m->loss})
+    if (q) (void)hipFree(q);
+  delete m;
+}
+
+lbm_status lbm_mlp_set_params(lbm_mlp* m, const float* params) {
+  if (!m || !params) return fail(LBM_EINVAL, "NULL argument");
+  const size_t np = mlp_param_count();
+  HIP_TRY(hipMemcpyAsync(m->p, params, np * 4, hipMemcpyHostToDevice, m->stream));
+  HIP_TRY(hipMemsetAsync(m->m, 0, np * 4, m->stream));
+  HIP_TRY(hipMemsetAsync(m->v, 0, np * 4, m->stream));
+  HIP_TRY(launch_mlp_round(m->p, m->wb, m->stream));
+  HIP_TRY(hipStreamSynchronize(m->stream));
+  m->adam_t = 0;
+  return LBM_OK;
+}
+
+lbm_status lbm_mlp_get_params(lbm_mlp* m, float* params) {
+  if (!m || !params) return fail(LBM_EINVAL, "NULL argument");
+  HIP_TRY(hipMemcpyAsync(params, m->p, (size_t)mlp_param_count() * 4, hipMemcpyDeviceToHost, m->stream));
+  HIP_TRY(hipStreamSynchronize(m->stream));
+  return LBM_OK;
+}
+
+lbm_status lbm_mlp_forward(lbm_mlp* m, const float* x, int32_t n, float* y) {
+  if (!m || !x || !y) return fail(LBM_EINVAL, "NULL argument");
+  lbm_status st = mlp_check_n(m, n);
+  if (st != LBM_OK) return st;
+  HIP_TRY(hipMemcpyAsync(m->x, x, (size_t)n * 12, hipMemcpyHostToDevice, m->stream));
+  HIP_TRY(launch_mlp_forward(m->x, n, m->p, m->wb, nullptr, m->y, m->stream));
+  HIP_TRY(hipMemcpyAsync(y, m->y, (size_t)n * 12, hipMemcpyDeviceToHost, m->stream));
+  HIP_TRY(hipStreamSynchronize(m->stream));
+  return LBM_OK;
+}
+
+lbm_status lbm_mlp_backward(lbm_mlp* m, const float* x, const float* dy, int32_t n, float* grad,
+                            float* dx) {
+  if (!m || !x || !dy) return fail(LBM_EINVAL, "NULL argument");
+  lbm_status st = mlp_check_n(m, n);
+  if (st != LBM_OK) return st;
+  HIP_TRY(hipMemcpyAsync(m->x, x, (size_t)n * 12, hipMemcpyHostToDevice, m->stream));
+  HIP_TRY(hipMemcpyAsync(m->dy, dy, (size_t)n * 12, hipMemcpyHostToDevice, m->stream));
+  HIP_TRY(launch_mlp_forward(m->x, n, m->p, m->wb, m->acts, m->y, m->stream));
+  HIP_TRY(launch_mlp_backward(m->x, m->acts, m->dy, n, m->wb, m->gpart, m->grad, m->dx, m->stream));
+  if (grad) HIP_TRY(hipMemcpyAsync(grad, m->grad, (size_t)mlp_param_count() * 4, hipMemcpyDeviceToHost, m->stream));
+  if (dx) HIP_TRY(hipMemcpyAsync(dx, m->dx, (size_t)n * 12, hipMemcpyDeviceToHost, m->stream));
+  HIP_TRY(hipStreamSynchronize(m->stream));
+  return LBM_OK;
+}
+
+lbm_status lbm_mlp_set_data(lbm_mlp* m, const float* x, const float* t, int32_t n) {
+  if (!m || !x || !t) return fail(LBM_EINVAL, "NULL argument");
+  lbm_status st = mlp_check_n(m, n);
+  if (st != LBM_OK) return st;
+  HIP_TRY(hipMemcpyAsync(m->x, x, (size_t)n * 12, hipMemcpyHostToDevice, m->stream));
+  HIP_TRY(hipMemcpyAsync(m->t, t, (size_t)n * 12, hipMemcpyHostToDevice, m->stream));
+  HIP_TRY(hipStreamSynchronize(m->stream));
+  m->ndata = n;
+  return LBM_OK;
+}
+
+lbm_status lbm_mlp_train(lbm_mlp* m, int32_t iters, float lr, float* loss_out) {
+  if (!m) return fail(LBM_EINVAL, "NULL argument");
+  if (m->ndata < 1) return fail(LBM_ESTATE, "lbm_mlp_train before lbm_mlp_set_data");
+  if (iters < 0 || !(lr > 0.f)) return fail(LBM_EINVAL, "iters must be >= 0 and lr > 0");
+  if (iters > m->loss_cap) {
+    if (m->loss) HIP_TRY(hipFree(m->loss));
+    m->loss = nullptr;
+    HIP_TRY(hipMalloc(&m->loss, (size_t)iters * 4));
+    m->loss_cap = iters;
+  }
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  for (int it = 0; it < iters; ++it) {
+    ++m->adam_t;
+    const float c1 = 1.f - std::pow(b1, (float)m->adam_t), c2 = 1.f - std::pow(b2, (float)m->adam_t);
+    HIP_TRY(launch_mlp_forward(m->x, m->ndata, m->p, m->wb, m->acts, m->y, m->stream));
+    HIP_TRY(launch_mlp_mse(m->y, m->t, m->ndata, m->dy, m->loss + it, m->stream));
+    HIP_TRY(launch_mlp_backward(m->x, m->acts, m->dy, m->ndata, m->wb, m->gpart, m->grad, nullptr, m->stream));
+    HIP_TRY(launch_mlp_adam(m->p, m->m, m->v, m->grad, m->wb, lr, b1, b2, eps, c1, c2, m->stream));
+  }
+  if (loss_out && iters > 0)
+    HIP_TRY(hipMemcpyAsync(loss_out, m->loss, (size_t)iters * 4, hipMemcpyDeviceToHost, m->stream));
+  HIP_TRY(hipStreamSynchronize(m->stream));
+  return LBM_OK;
+}
 
 }  // extern "C"

@@ -35,6 +35,9 @@ struct ModelConsts {
 hipError_t launch_step(lbm_precision prec, const Geometry& g, const ModelConsts& m, const void* fa,
                        void* fb, hipStream_t s);
 
+// Workgroups of the step kernel (for g.tile_x) that one CU holds at once.
+hipError_t step_occupancy(lbm_precision prec, const Geometry& g, int eos, int* per_cu);
+
 // f = equilibrium(rho, u) from device FP64 arrays [ny][nx] (ux/uy may be null).
 hipError_t launch_init_equilibrium(lbm_precision prec, const Geometry& g, const double* rho,
                                    const double* ux, const double* uy, void* f, hipStream_t s);
@@ -61,5 +64,31 @@ int obs_partials_count(const Geometry& g);
 hipError_t launch_observables(lbm_precision prec, const Geometry& g, const ModelConsts& m,
                               const void* f, const double* work, double* partials, double* red,
                               hipStream_t s);
+
+// Batched engine (lbm_batch.hip).  Descriptors and tiles are opaque records
+// filled on the host and copied to the device.
+size_t batch_domain_bytes(lbm_precision prec);
+size_t batch_tile_bytes();
+void batch_fill_domain(lbm_precision prec, const Geometry& g, const ModelConsts& m, void* fa,
+                       void* fb, unsigned ntiles, void* out);
+void batch_fill_tile(int domain, int x0, int y0, int down, void* out);
+hipError_t batch_occupancy(lbm_precision prec, int eos, int tile_x, int* per_cu);
+hipError_t launch_batch(lbm_precision prec, int eos, int tile_x, bool persistent, const void* dom,
+                        const void* tiles, const int* wg_begin, unsigned* done, int* err, int grid,
+                        int nsteps, int parity, long long spin_limit, hipStream_t s);
+hipError_t launch_batch_reset(unsigned* done, int n, int* err, hipStream_t s);
+
+// Surrogate network (lbm_mlp.hip).
+int mlp_param_count();
+int mlp_rows_per_block();
+hipError_t launch_mlp_forward(const float* x, int B, const float* master, const unsigned short* wb,
+                              float* acts, float* y, hipStream_t s);
+hipError_t launch_mlp_backward(const float* x, const float* acts, const float* dy, int B,
+                               const unsigned short* wb, float* gpart, float* grad, float* dx,
+                               hipStream_t s);
+hipError_t launch_mlp_mse(const float* y, const float* t, int B, float* dy, float* loss, hipStream_t s);
+hipError_t launch_mlp_adam(float* p, float* m, float* v, const float* g, unsigned short* wb, float lr,
+                           float b1, float b2, float eps, float c1, float c2, hipStream_t s);
+hipError_t launch_mlp_round(const float* p, unsigned short* wb, hipStream_t s);
 
 }  // namespace lbm

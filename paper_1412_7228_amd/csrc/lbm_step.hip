@@ -1,177 +1,19 @@
-// Fused time step of the pseudo-potential MRT lattice Boltzmann model on gfx950.
-//
-// One kernel does the whole step (density/psi pass, Kupershtokh force,
-// pressure-tensor term, MRT collision, streaming) with A/B buffers:
-//
-//  * Pull streaming: cell x gathers f_a(x - e_a) from buffer A and writes its
-//    post-collision f*_a(x) to buffer B at x, so every load and every store of
-//    a wavefront is a contiguous (at most one element off) run of one plane.
-//  * A workgroup of tile_x threads owns a strip of tile_x columns and marches
-//    up tile_y rows.  For each row it gathers f, forms rho, U and psi (Eq. 10)
-//    and puts (U, psi) into a 4-row ring in LDS; after one barrier the row
-//    below has its full 3x3 stencil and is collided and stored.  The strip's
-//    two edge columns of (U, psi) are recomputed by two lanes; the first and
-//    last row of a tile are recomputed (not stored), so no intermediate field
-//    ever goes to HBM: 9 loads + 9 stores per cell per step.
-//  * Row offsets are uniform across the workgroup (scalar registers); only the
-//    column index is per lane.
-#include "lbm_device.h"
+// Single-lattice time step: one launch of k_step per step.
+#include "lbm_tile.h"
 
 namespace lbm {
 
-// Buffer resource of one distribution plane (gfx9 raw buffer, 32-bit
-// offsets).  Loads through it take the row offset in a scalar register and
-// the column offset in a vector register, so no per-lane 64-bit address
-// arithmetic is needed; an offset past the plane reads 0 instead of faulting.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* base, unsigned bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, 0x00020000);
-}
-
-typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
-
-template <typename T>
-__device__ __forceinline__ T ld(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
-  if constexpr (sizeof(T) == 4) {
-    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
-  } else {
-    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
-  }
-}
-
-template <typename T>
-__device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, T v) {
-  if constexpr (sizeof(T) == 4) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)voff, (int)soff, 0);
-  } else {
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)voff, (int)soff, 0);
-  }
-}
-
-// The distribution buffers as seen by the step kernel.  A buffer below 4 GiB
-// is one resource and the plane offset goes into the scalar offset; a larger
-// one gets one resource per plane.
-template <bool BIG>
-struct Planes {
-  __amdgpu_buffer_rsrc_t r[BIG ? 9 : 1];
-  unsigned plane_bytes;
-  __device__ __forceinline__ void init(const void* base, unsigned long long plane_b) {
-    if constexpr (BIG) {
-#pragma unroll
-      for (int a = 0; a < 9; ++a)
-        r[a] = plane_rsrc(static_cast<const char*>(base) + a * plane_b, (unsigned)plane_b);
-    } else {
-      r[0] = plane_rsrc(base, (unsigned)(9 * plane_b));
-    }
-    plane_bytes = (unsigned)plane_b;
-  }
-  __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(int a) const { return r[BIG ? a : 0]; }
-  __device__ __forceinline__ unsigned soff(int a, unsigned row) const {
-    return BIG ? row : a * plane_bytes + row;
-  }
-};
-
-// f_a(x - e_a) for the 9 velocities, gathered at row r.  rr, rm, rp are the
-// byte offsets of rows r, r - 1, r + 1 within a plane (uniform); ox, oxm, oxp
-// the byte offsets of columns x, x - 1, x + 1 (per lane).
-template <typename T, bool BIG>
-__device__ __forceinline__ void gather(const Planes<BIG>& pa, unsigned rr, unsigned rm,
-                                       unsigned rp, unsigned ox, unsigned oxm, unsigned oxp,
-                                       T (&g)[9]) {
-  g[0] = ld<T>(pa.rsrc(0), ox, pa.soff(0, rr));
-  g[1] = ld<T>(pa.rsrc(1), oxm, pa.soff(1, rr));  // e_1 = ( 1, 0)
-  g[2] = ld<T>(pa.rsrc(2), ox, pa.soff(2, rm));   // e_2 = ( 0, 1)
-  g[3] = ld<T>(pa.rsrc(3), oxp, pa.soff(3, rr));  // e_3 = (-1, 0)
-  g[4] = ld<T>(pa.rsrc(4), ox, pa.soff(4, rp));   // e_4 = ( 0,-1)
-  g[5] = ld<T>(pa.rsrc(5), oxm, pa.soff(5, rm));  // e_5 = ( 1, 1)
-  g[6] = ld<T>(pa.rsrc(6), oxp, pa.soff(6, rm));  // e_6 = (-1, 1)
-  g[7] = ld<T>(pa.rsrc(7), oxp, pa.soff(7, rp));  // e_7 = (-1,-1)
-  g[8] = ld<T>(pa.rsrc(8), oxm, pa.soff(8, rp));  // e_8 = ( 1,-1)
-}
-
-template <typename T>
-__device__ __forceinline__ T density(const T (&g)[9]) {
-  return g[0] + ((g[1] + g[3]) + (g[2] + g[4])) + ((g[5] + g[7]) + (g[6] + g[8]));
-}
-
+// One time step over the whole lattice: workgroup -> tile with the strips of
+// a row block consecutive (so x-neighbours share an XCD), row blocks
+// alternating their march direction.
 template <typename T, int EOS, int BX, bool BIG>
 __global__ void __launch_bounds__(BX) k_step(const T* __restrict__ fa, T* __restrict__ fb,
                                               const Geometry geo, const DevC<T> c) {
-  using T2 = typename V2<T>::t;
-  __shared__ T2 ring[4][BX + 2];
-
-  const int nx = geo.nx, ny = geo.ny;
-  const long long P = geo.plane;
-  const long long pitch = geo.pitch;
+  __shared__ typename V2<T>::t ring[4][BX + 2];
   const int lb = xcd_remap(blockIdx.x, geo.nblocks);
-  const int strip = lb / geo.nrowblocks;
-  const int rb = lb - strip * geo.nrowblocks;
-  const int x0 = strip * BX, y0 = rb * geo.tile_y;
-  const int W = min(BX, nx - x0), H = min(geo.tile_y, ny - y0);
-  const int tx = threadIdx.x;
-  const bool active = tx < W;
-  const int x = x0 + (active ? tx : W - 1);  // idle lanes gather a valid column
-  const unsigned sz = sizeof(T);
-  const unsigned ox = x * sz;
-  const unsigned oxm = ((x == 0) ? nx - 1 : x - 1) * sz;
-  const unsigned oxp = ((x == nx - 1) ? 0 : x + 1) * sz;
-  // lanes 0 and 1 also produce the strip's left / right edge column
-  const bool edge = tx < 2;
-  const int hx = (tx == 0) ? (x0 == 0 ? nx - 1 : x0 - 1) : (x0 + W == nx ? 0 : x0 + W);
-  const unsigned ohx = hx * sz;
-  const unsigned ohxm = ((hx == 0) ? nx - 1 : hx - 1) * sz;
-  const unsigned ohxp = ((hx == nx - 1) ? 0 : hx + 1) * sz;
-  const int hslot = (tx == 0) ? 0 : W + 1;
-
-  const unsigned row_bytes = (unsigned)(pitch * sz);
-  Planes<BIG> pa, pb;
-  pa.init(fa, (unsigned long long)P * sz);
-  pb.init(fb, (unsigned long long)P * sz);
-
-  T fc[9];
-  T rho_c = T(0);
-#pragma unroll 1
-  for (int i = 0; i < H + 2; ++i) {
-    const int r = y0 - 1 + i;
-    const unsigned rr = wrap_(r, ny) * row_bytes;
-    const unsigned rm = wrap_(r - 1, ny) * row_bytes;
-    const unsigned rp = wrap_(r + 1, ny) * row_bytes;
-    T g[9];
-    gather(pa, rr, rm, rp, ox, oxm, oxp, g);
-    const T rho = density(g);
-    const T U = eos_U<EOS>(rho, c);
-    const int slot = i & 3;
-    if (active) ring[slot][tx + 1] = T2{U, psi_of(U, c)};
-    if (edge) {
-      T h[9];
-      gather(pa, rr, rm, rp, ohx, ohxm, ohxp, h);
-      const T Uh = eos_U<EOS>(density(h), c);
-      ring[slot][hslot] = T2{Uh, psi_of(Uh, c)};
-    }
-    __syncthreads();
-    if (i >= 2 && active) {
-      // stencil of row r - 1: south = row r - 2, north = row r
-      const int ss = (i - 2) & 3, sc = (i - 1) & 3, sn = slot;
-      T Un[9], Pn[9];
-      T2 v;
-      v = ring[sc][tx + 1]; Un[0] = v.x; Pn[0] = v.y;
-      v = ring[sc][tx + 2]; Un[1] = v.x; Pn[1] = v.y;  // ( 1, 0)
-      v = ring[sn][tx + 1]; Un[2] = v.x; Pn[2] = v.y;  // ( 0, 1)
-      v = ring[sc][tx];     Un[3] = v.x; Pn[3] = v.y;  // (-1, 0)
-      v = ring[ss][tx + 1]; Un[4] = v.x; Pn[4] = v.y;  // ( 0,-1)
-      v = ring[sn][tx + 2]; Un[5] = v.x; Pn[5] = v.y;  // ( 1, 1)
-      v = ring[sn][tx];     Un[6] = v.x; Pn[6] = v.y;  // (-1, 1)
-      v = ring[ss][tx];     Un[7] = v.x; Pn[7] = v.y;  // (-1,-1)
-      v = ring[ss][tx + 2]; Un[8] = v.x; Pn[8] = v.y;  // ( 1,-1)
-      T out[9];
-      collide_cell(fc, rho_c, Un, Pn, c, out);
-      const unsigned ro = (unsigned)(r - 1) * row_bytes;
-#pragma unroll
-      for (int a = 0; a < 9; ++a) st<T>(pb.rsrc(a), ox, pb.soff(a, ro), out[a]);
-    }
-#pragma unroll
-    for (int a = 0; a < 9; ++a) fc[a] = g[a];
-    rho_c = rho;
-  }
+  const int rb = lb / geo.nstrips;
+  const int strip = lb - rb * geo.nstrips;
+  step_tile<T, EOS, BX, BIG>(fa, fb, geo, c, strip * BX, rb * geo.tile_y, (rb & 1) != 0, ring);
 }
 
 template <typename T, int EOS, bool BIG>
@@ -215,6 +57,37 @@ static hipError_t launch_step_p(const Geometry& g, const ModelConsts& m, const v
     case LBM_EOS_PR: return launch_step_t<T, LBM_EOS_PR>(g, c, fa, fb, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+template <typename T, int EOS>
+static hipError_t occupancy_e(int bx, bool big, int* per_cu) {
+#define LBM_OCC(B)                                                                              \
+  if (bx == B)                                                                                  \
+    return big ? hipOccupancyMaxActiveBlocksPerMultiprocessor(                                  \
+                     per_cu, reinterpret_cast<const void*>(&k_step<T, EOS, B, true>), B, 0)     \
+               : hipOccupancyMaxActiveBlocksPerMultiprocessor(                                  \
+                     per_cu, reinterpret_cast<const void*>(&k_step<T, EOS, B, false>), B, 0);
+  LBM_OCC(64) LBM_OCC(128) LBM_OCC(256)
+#undef LBM_OCC
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+static hipError_t occupancy_t(int eos, int bx, bool big, int* per_cu) {
+  switch (eos) {
+    case LBM_EOS_IDEAL: return occupancy_e<T, LBM_EOS_IDEAL>(bx, big, per_cu);
+    case LBM_EOS_CS: return occupancy_e<T, LBM_EOS_CS>(bx, big, per_cu);
+    case LBM_EOS_VDW: return occupancy_e<T, LBM_EOS_VDW>(bx, big, per_cu);
+    case LBM_EOS_PR: return occupancy_e<T, LBM_EOS_PR>(bx, big, per_cu);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t step_occupancy(lbm_precision prec, const Geometry& g, int eos, int* per_cu) {
+  const size_t es = prec == LBM_FP32 ? 4 : 8;
+  const bool big = 9ull * (unsigned long long)g.plane * es >= (1ull << 32);
+  if (prec == LBM_FP32) return occupancy_t<float>(eos, g.tile_x, big, per_cu);
+  return occupancy_t<double>(eos, g.tile_x, big, per_cu);
 }
 
 hipError_t launch_step(lbm_precision prec, const Geometry& g, const ModelConsts& m, const void* fa,

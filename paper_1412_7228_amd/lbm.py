@@ -64,14 +64,26 @@ class Launch(ctypes.Structure):
     _fields_ = [("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32)]
 
 
+class BatchLaunch(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32),
+                ("spin_limit", ctypes.c_int64), ("force_spin_limit", ctypes.c_int32),
+                ("grid", ctypes.c_int32), ("ntiles", ctypes.c_int32),
+                ("resident_per_cu", ctypes.c_int32)]
+
+
+BATCH_MODES = {"persistent": 0, "per_step": 1}
+
+
 _lib = None
 
 
-def load_library(path: str = LIB_PATH):
-    """Load liblbm.so and declare its entry points.  Raises if it is not built."""
+def load_library(path: str | None = None):
+    """Load liblbm.so (``LIB_PATH`` unless given) and declare its entry points.
+    Raises if it is not built."""
     global _lib
     if _lib is not None:
         return _lib
+    path = path or LIB_PATH
     if not os.path.exists(path):
         raise FileNotFoundError(f"{path} is not built (python -m paper_1412_7228_amd.build)")
     lib = ctypes.CDLL(path)
@@ -98,6 +110,15 @@ def load_library(path: str = LIB_PATH):
         "lbm_sync": (st, [vp]),
         "lbm_state_info": (st, [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(vp),
                                 ctypes.POINTER(ctypes.c_int32)]),
+        "lbm_batch_create": (st, [P, ctypes.c_int32, vp, ctypes.POINTER(vp)]),
+        "lbm_batch_destroy": (None, [vp]),
+        "lbm_batch_set_launch": (st, [vp, ctypes.POINTER(BatchLaunch)]),
+        "lbm_batch_get_launch": (st, [vp, ctypes.POINTER(BatchLaunch)]),
+        "lbm_batch_init_field": (st, [vp, ctypes.c_int32, dp, dp, dp]),
+        "lbm_batch_step": (st, [vp, ctypes.c_int64]),
+        "lbm_batch_sync": (st, [vp]),
+        "lbm_batch_observables": (st, [vp, ctypes.POINTER(Obs)]),
+        "lbm_batch_get_field": (st, [vp, ctypes.c_int32, ctypes.c_int32, dp]),
         "lbm_strerror": (ctypes.c_char_p, [st]),
         "lbm_last_error": (ctypes.c_char_p, []),
     }
@@ -261,3 +282,85 @@ class Lattice:
         _check(self.lib.lbm_state_info(self.h, ctypes.byref(step), ctypes.byref(ptr),
                                        ctypes.byref(pitch)))
         return dict(step=step.value, f_cur=ptr.value, pitch=pitch.value)
+
+
+class Batch:
+    """Many independent lattices advanced together (``lbm_batch_*``).
+
+    ``cfgs``: one parameter dict per domain (same EOS kind and precision).
+    """
+
+    def __init__(self, cfgs: list, stream=None):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("liblbm needs a HIP device; none is visible")
+        self.lib = load_library()
+        self.cfgs = [dict(DEFAULTS, **c) for c in cfgs]
+        arr = (Params * len(cfgs))(*[make_params(c) for c in cfgs])
+        self._params = arr
+        self.shapes = [(p.ny, p.nx) for p in arr]
+        # a stream of its own (default priority), so the library can use HIP graphs
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        h = ctypes.c_void_p()
+        _check(self.lib.lbm_batch_create(arr, len(cfgs), ctypes.c_void_p(self.stream.cuda_stream),
+                                         ctypes.byref(h)))
+        self.h = h
+        self.n = len(cfgs)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.lbm_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_launch(self, mode: str = "per_step", tile_x: int = 0, tile_y: int = 0,
+                   spin_limit: int = 0, force_spin_limit: bool = False):
+        l = BatchLaunch(BATCH_MODES[mode], int(tile_x), int(tile_y), int(spin_limit),
+                        int(force_spin_limit), 0, 0, 0)
+        _check(self.lib.lbm_batch_set_launch(self.h, ctypes.byref(l)))
+
+    @property
+    def launch(self) -> dict:
+        l = BatchLaunch()
+        _check(self.lib.lbm_batch_get_launch(self.h, ctypes.byref(l)))
+        inv = {v: k for k, v in BATCH_MODES.items()}
+        return dict(mode=inv[l.mode], tile_x=l.tile_x, tile_y=l.tile_y, spin_limit=l.spin_limit,
+                    grid=l.grid, ntiles=l.ntiles, resident_per_cu=l.resident_per_cu)
+
+    def init_field(self, i: int, rho, ux=None, uy=None):
+        shp = self.shapes[i]
+        r = np.ascontiguousarray(rho, dtype=np.float64).reshape(shp)
+        u = None if ux is None else np.ascontiguousarray(ux, dtype=np.float64).reshape(shp)
+        v = None if uy is None else np.ascontiguousarray(uy, dtype=np.float64).reshape(shp)
+        null = ctypes.POINTER(ctypes.c_double)()
+        _check(self.lib.lbm_batch_init_field(self.h, int(i), _dptr(r),
+                                             _dptr(u) if u is not None else null,
+                                             _dptr(v) if v is not None else null))
+
+    def step(self, n: int = 1):
+        _check(self.lib.lbm_batch_step(self.h, int(n)))
+        return self
+
+    def sync(self):
+        _check(self.lib.lbm_batch_sync(self.h))
+
+    def observables(self, check: bool = False) -> list:
+        out = (Obs * self.n)()
+        st = self.lib.lbm_batch_observables(self.h, out)
+        if check or st in (-1, -2, -3, -6):
+            _check(st)
+        return [{k: getattr(o, k) for k, _ in Obs._fields_} for o in out]
+
+    def field(self, i: int, name: str) -> np.ndarray:
+        out = np.empty(self.shapes[i])
+        _check(self.lib.lbm_batch_get_field(self.h, int(i), FIELDS[name], _dptr(out)))
+        return out
+
+    def f_soa(self, i: int) -> np.ndarray:
+        return np.stack([self.field(i, f"f{a}") for a in range(9)])
