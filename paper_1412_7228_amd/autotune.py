@@ -1,0 +1,110 @@
+"""Launch-shape autotuner for the step kernel and the batched engine.
+
+Times candidate launch shapes on the GPU it runs on (HIP events on the
+lattice's stream) and keeps the fastest.  Results are cached as JSON, keyed by
+the device name and the workload's signature (lattice size, precision, EOS;
+for a batch the sorted domain sizes), in ``$LBM_TUNE_CACHE`` or
+``~/.cache/paper_1412_7228_amd/tune.json``.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+LATTICE_CANDIDATES = [(256, 8), (256, 16), (256, 32), (256, 64), (256, 128), (128, 16), (128, 32),
+                      (128, 64), (64, 32), (64, 64)]
+BATCH_CANDIDATES = [("per_step", 64, 16), ("per_step", 64, 32), ("per_step", 64, 64),
+                    ("per_step", 128, 32), ("per_step", 128, 64), ("persistent", 64, 32),
+                    ("persistent", 64, 64), ("persistent", 128, 64)]
+
+
+def cache_path() -> str:
+    return os.environ.get("LBM_TUNE_CACHE") or os.path.join(
+        os.path.expanduser("~"), ".cache", "paper_1412_7228_amd", "tune.json")
+
+
+def _load() -> dict:
+    try:
+        with open(cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(cache: dict):
+    p = cache_path()
+    try:
+        os.makedirs(os.path.dirname(p), exist_ok=True)
+        with open(p + ".tmp", "w") as f:
+            json.dump(cache, f, indent=1)
+        os.replace(p + ".tmp", p)
+    except OSError:
+        pass  # a read-only home only loses the cache
+
+
+def _device() -> str:
+    import torch
+
+    return torch.cuda.get_device_name(0)
+
+
+def _time(stream, fn, steps: int) -> float:
+    import torch
+
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    fn(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def tune_lattice(lat, steps: int = 40, candidates=None, use_cache: bool = True) -> dict:
+    """Pick the fastest (tile_x, tile_y) for a Lattice (its state advances by the
+    timing steps).  Returns {"tile": [tx, ty], "ms": ..., "table": [...]}."""
+    c = lat.cfg
+    key = f"lattice|{_device()}|{lat.nx}x{lat.ny}|{c['precision']}|{c['eos']}"
+    cache = _load() if use_cache else {}
+    if key in cache:
+        lat.set_launch(*cache[key]["tile"])
+        return cache[key]
+    table = []
+    for tx, ty in candidates or LATTICE_CANDIDATES:
+        if tx > 64 and lat.nx < tx:
+            continue
+        lat.set_launch(tx, min(ty, lat.ny))
+        lat.step(5)
+        table.append(((tx, min(ty, lat.ny)), _time(lat.stream, lat.step, steps)))
+    best = min(table, key=lambda t: t[1])
+    lat.set_launch(*best[0])
+    res = {"tile": list(best[0]), "ms": best[1], "table": [[list(t), m] for t, m in table]}
+    cache[key] = res
+    _store(cache)
+    return res
+
+
+def tune_batch(batch, steps: int = 20, candidates=None, use_cache: bool = True) -> dict:
+    """Pick the fastest (mode, tile_x, tile_y) for a Batch (its state advances)."""
+    sizes = sorted(f"{ny}x{nx}" for ny, nx in batch.shapes)
+    sig = str(abs(hash(",".join(sizes))) % (10 ** 12))
+    c = batch.cfgs[0]
+    key = f"batch|{_device()}|{len(sizes)}|{sig}|{c['precision']}|{c['eos']}"
+    cache = _load() if use_cache else {}
+    if key in cache:
+        batch.set_launch(*cache[key]["launch"])
+        return cache[key]
+    table = []
+    for mode, tx, ty in candidates or BATCH_CANDIDATES:
+        batch.set_launch(mode, tx, ty)
+        batch.step(2)
+        batch.sync()
+        ms = _time(batch.stream, batch.step, steps)
+        batch.sync()
+        table.append(((mode, tx, ty), ms))
+    best = min(table, key=lambda t: t[1])
+    batch.set_launch(*best[0])
+    res = {"launch": list(best[0]), "ms": best[1], "table": [[list(t), m] for t, m in table]}
+    cache[key] = res
+    _store(cache)
+    return res

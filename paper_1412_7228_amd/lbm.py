@@ -88,6 +88,7 @@ def load_library(path: str | None = None):
         raise FileNotFoundError(f"{path} is not built (python -m paper_1412_7228_amd.build)")
     lib = ctypes.CDLL(path)
     vp, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)
+    fp = ctypes.POINTER(ctypes.c_float)
     P = ctypes.POINTER(Params)
     st = ctypes.c_int
     decl = {
@@ -119,6 +120,15 @@ def load_library(path: str | None = None):
         "lbm_batch_sync": (st, [vp]),
         "lbm_batch_observables": (st, [vp, ctypes.POINTER(Obs)]),
         "lbm_batch_get_field": (st, [vp, ctypes.c_int32, ctypes.c_int32, dp]),
+        "lbm_mlp_param_count": (ctypes.c_int32, []),
+        "lbm_mlp_create": (st, [ctypes.c_int32, vp, ctypes.POINTER(vp)]),
+        "lbm_mlp_destroy": (None, [vp]),
+        "lbm_mlp_set_params": (st, [vp, fp]),
+        "lbm_mlp_get_params": (st, [vp, fp]),
+        "lbm_mlp_forward": (st, [vp, fp, ctypes.c_int32, fp]),
+        "lbm_mlp_backward": (st, [vp, fp, fp, ctypes.c_int32, fp, fp]),
+        "lbm_mlp_set_data": (st, [vp, fp, fp, ctypes.c_int32]),
+        "lbm_mlp_train": (st, [vp, ctypes.c_int32, ctypes.c_float, fp]),
         "lbm_strerror": (ctypes.c_char_p, [st]),
         "lbm_last_error": (ctypes.c_char_p, []),
     }
@@ -364,3 +374,75 @@ class Batch:
 
     def f_soa(self, i: int) -> np.ndarray:
         return np.stack([self.field(i, f"f{a}") for a in range(9)])
+
+
+def _fptr(a: np.ndarray):
+    assert a.dtype == np.float32 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+class MLP:
+    """The surrogate network of the library (``lbm_mlp_*``): 3 -> 128 -> 128 -> 128 -> 3."""
+
+    def __init__(self, max_batch: int = 1024, stream=None):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("liblbm needs a HIP device; none is visible")
+        self.lib = load_library()
+        self.nparams = int(self.lib.lbm_mlp_param_count())
+        self.max_batch = int(max_batch)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        _check(self.lib.lbm_mlp_create(self.max_batch, ctypes.c_void_p(self.stream.cuda_stream),
+                                       ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.lbm_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        assert p.size == self.nparams
+        _check(self.lib.lbm_mlp_set_params(self.h, _fptr(p)))
+
+    def params(self) -> np.ndarray:
+        out = np.empty(self.nparams, dtype=np.float32)
+        _check(self.lib.lbm_mlp_get_params(self.h, _fptr(out)))
+        return out
+
+    def forward(self, x) -> np.ndarray:
+        x = np.ascontiguousarray(x, dtype=np.float32).reshape(-1, 3)
+        out = np.empty_like(x)
+        for i in range(0, len(x), self.max_batch):
+            xs = np.ascontiguousarray(x[i:i + self.max_batch])
+            ys = np.empty_like(xs)
+            _check(self.lib.lbm_mlp_forward(self.h, _fptr(xs), len(xs), _fptr(ys)))
+            out[i:i + len(xs)] = ys
+        return out
+
+    def backward(self, x, dy):
+        x = np.ascontiguousarray(x, dtype=np.float32).reshape(-1, 3)
+        dy = np.ascontiguousarray(dy, dtype=np.float32).reshape(-1, 3)
+        grad = np.empty(self.nparams, dtype=np.float32)
+        dx = np.empty_like(x)
+        _check(self.lib.lbm_mlp_backward(self.h, _fptr(x), _fptr(dy), len(x), _fptr(grad), _fptr(dx)))
+        return grad, dx
+
+    def set_data(self, x, t):
+        x = np.ascontiguousarray(x, dtype=np.float32).reshape(-1, 3)
+        t = np.ascontiguousarray(t, dtype=np.float32).reshape(-1, 3)
+        _check(self.lib.lbm_mlp_set_data(self.h, _fptr(x), _fptr(t), len(x)))
+
+    def train(self, iters: int, lr: float) -> np.ndarray:
+        loss = np.empty(max(1, iters), dtype=np.float32)
+        _check(self.lib.lbm_mlp_train(self.h, int(iters), float(lr), _fptr(loss)))
+        return loss[:iters]

@@ -1,0 +1,242 @@
+"""Surrogate-guided surface-tension tuning (method 2 of Sec. 3.2 with a learned model).
+
+A small network (the library's ``lbm_mlp_*`` kernels) maps
+(A, kappa, T/Tc) -> (sigma, rho_l, rho_v) and is trained on droplet runs of
+the batched engine.  To reach a target surface tension sigma* at a given
+(A, T/Tc), the network is inverted for kappa and the prediction is checked
+by one real lattice run; if that run misses by more than 2 %, the plain
+kappa sweep is the fallback.  Two baselines without the network are counted
+the same way: the plain sweep (kappa on a 0.1 grid over [0, 0.8], bracket,
+interpolate, verify) and the secant guided by Eq. (28)'s sigma proportional
+to (1 - kappa) (a kappa = 0 run, then kappa = 1 - sigma*/sigma_0, verify,
+then secant updates).
+
+    python -m paper_1412_7228_amd.surrogate --out report.json
+
+runs the whole study on the GPU (training set from uneven droplet batches,
+64 targets, every verification a 200 x 200 droplet of radius 40 run for
+20,000 steps) and writes a JSON report.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import time
+
+import numpy as np
+
+from . import inputs, laplace, lbm
+
+FEATURE_LO = np.array([-0.7, 0.0, 0.6])   # A, kappa, T/Tc
+FEATURE_HI = np.array([-0.3, 0.8, 0.85])
+KAPPA_RANGE = (0.0, 0.8)
+TOLERANCE = 0.02
+
+
+def features(A, kappa, T) -> np.ndarray:
+    v = np.stack([np.asarray(A, float), np.asarray(kappa, float), np.asarray(T, float)], axis=-1)
+    return (2.0 * (v - FEATURE_LO) / (FEATURE_HI - FEATURE_LO) - 1.0).astype(np.float32)
+
+
+def init_params(seed: int, nparams: int = 33923) -> np.ndarray:
+    """Uniform(+-1/sqrt(fan_in)) initial weights and biases for 3-128-128-128-3."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    sizes = (3, 128, 128, 128, 3)
+    parts = []
+    for i in range(4):
+        s = 1.0 / math.sqrt(sizes[i])
+        parts.append(g.uniform(-s, s, sizes[i] * sizes[i + 1]))
+        parts.append(g.uniform(-s, s, sizes[i + 1]))
+    p = np.concatenate(parts).astype(np.float32)
+    assert p.size == nparams
+    return p
+
+
+class Surrogate:
+    """(A, kappa, T/Tc) -> (sigma, rho_l, rho_v) through the library's network kernels.
+    Targets are learned as (log sigma, rho_l, log rho_v), standardised."""
+
+    def __init__(self, seed: int = 0, max_batch: int = 1024):
+        self.net = lbm.MLP(max_batch=max_batch)
+        self.net.set_params(init_params(seed, self.net.nparams))
+        self.mu = np.zeros(3)
+        self.sd = np.ones(3)
+
+    @staticmethod
+    def _targets(Y):
+        Y = np.asarray(Y, float)
+        return np.stack([np.log(Y[:, 0]), Y[:, 1], np.log(Y[:, 2])], axis=1)
+
+    def fit(self, X, Y, iters: int = 4000, lr: float = 2e-3) -> np.ndarray:
+        """X: [n, 3] (A, kappa, T/Tc); Y: [n, 3] (sigma, rho_l, rho_v).  Full-batch Adam."""
+        t = self._targets(Y)
+        self.mu, self.sd = t.mean(0), t.std(0) + 1e-12
+        X = np.asarray(X, float)
+        self.net.set_data(features(X[:, 0], X[:, 1], X[:, 2]), ((t - self.mu) / self.sd).astype(np.float32))
+        return self.net.train(iters, lr)
+
+    def predict(self, A, kappa, T) -> np.ndarray:
+        y = self.net.forward(features(A, kappa, T)).astype(float) * self.sd + self.mu
+        return np.stack([np.exp(y[:, 0]), y[:, 1], np.exp(y[:, 2])], axis=1)
+
+    def invert_kappa(self, A, T, sigma_target, grid: int = 801) -> np.ndarray:
+        """kappa in KAPPA_RANGE whose predicted sigma equals each target (linear
+        interpolation of log sigma on a dense kappa grid; clipped to the range)."""
+        A = np.atleast_1d(np.asarray(A, float))
+        T = np.atleast_1d(np.asarray(T, float))
+        st = np.atleast_1d(np.asarray(sigma_target, float))
+        ks = np.linspace(*KAPPA_RANGE, grid)
+        out = np.empty(len(A))
+        for i in range(len(A)):
+            s = self.predict(np.full(grid, A[i]), ks, np.full(grid, T[i]))[:, 0]
+            ls, lt = np.log(s), math.log(st[i])
+            # sigma falls with kappa (Eq. 28): interpolate on the decreasing sequence
+            order = np.argsort(ls)
+            out[i] = float(np.interp(lt, ls[order], ks[order]))
+        return np.clip(out, *KAPPA_RANGE)
+
+
+# ---------------------------------------------------------------------------
+# The study
+# ---------------------------------------------------------------------------
+def training_set(n_batches: int, seed: int, steps: int, side=(64, 512), domains: int = 256,
+                 log=print):
+    """Droplets drawn as in the uneven batch (side, R = u * side, T/Tc, kappa, A),
+    run in batches of `domains`; returns X [n, 3], Y [n, 3] of the runs that stayed
+    two-phase, and the count of draws outside the model's range."""
+    X, Y, bad = [], [], 0
+    for bi in range(n_batches):
+        draws = inputs.batch_draws(domains, seed + bi, side=side)
+        cases = [dict(n=d["nx"], R=d["R"], T_over_Tc=d["T_over_Tc"], A=d["A"], kappa=d["kappa"],
+                      seed=d["seed"]) for d in draws]
+        t0 = time.time()
+        res = laplace.run_cases(cases, steps, precision="fp32", mode="per_step", tile=(64, 32))
+        for r in res:
+            c = r["case"]
+            if r["ok"] and r["sigma"] > 0:
+                X.append((c["A"], c["kappa"], c["T_over_Tc"]))
+                Y.append((r["sigma"], r["rho_in"], r["rho_out"]))
+            else:
+                bad += 1
+        log(f"[surrogate] training batch {bi}: {sum(r['ok'] for r in res)}/{len(res)} two-phase, "
+            f"{time.time() - t0:.1f} s")
+    return np.array(X), np.array(Y), bad
+
+
+def verify(specs, steps: int, n: int = 200, R: float = 40.0):
+    """One LBM droplet run per (A, kappa, T/Tc) spec; returns sigma (nan if the run failed)."""
+    cases = [dict(n=n, R=R, A=a, kappa=k, T_over_Tc=t, seed=i) for i, (a, k, t) in enumerate(specs)]
+    res = laplace.run_cases(cases, steps, precision="fp32", mode="per_step", tile=(64, 32))
+    return np.array([r["sigma"] if r["ok"] else np.nan for r in res])
+
+
+def study(seed: int = 0, n_targets: int = 64, train_batches: int = 2, train_steps: int = 20000,
+          verify_steps: int = 20000, side=(64, 512), domains: int = 256, iters: int = 4000,
+          log=print) -> dict:
+    t_start = time.time()
+    X, Y, bad = training_set(train_batches, seed, train_steps, side=side, domains=domains, log=log)
+    sur = Surrogate(seed=seed)
+    loss = sur.fit(X, Y, iters=iters)
+    log(f"[surrogate] trained on {len(X)} runs: loss {loss[0]:.3e} -> {loss[-1]:.3e}")
+    # targets: (A, T/Tc) from the training distribution; sigma* = s sigma_0, s log-uniform in [0.2, 1]
+    g = inputs.rng(seed + 1000)
+    A = g.uniform(-0.7, -0.3, n_targets)
+    T = g.uniform(0.6, 0.85, n_targets)
+    s = np.exp(g.uniform(math.log(0.2), 0.0, n_targets))
+    sigma0 = verify([(a, 0.0, t) for a, t in zip(A, T)], verify_steps)
+    valid = np.isfinite(sigma0) & (sigma0 > 0)
+    target = s * sigma0
+    log(f"[surrogate] {valid.sum()}/{n_targets} targets two-phase at kappa = 0")
+    hit = lambda sig, tgt: np.isfinite(sig) & (np.abs(sig / tgt - 1.0) <= TOLERANCE)
+
+    # plain sweep: 9 runs per target on the kappa grid, interpolate, verify (10 runs)
+    kgrid = np.round(np.arange(0.0, 0.8001, 0.1), 10)
+    specs = [(a, k, t) for a, t in zip(A, T) for k in kgrid]
+    sweep_sig = verify(specs, verify_steps).reshape(n_targets, len(kgrid))
+
+    def from_sweep(i):
+        sg = sweep_sig[i]
+        ok = np.isfinite(sg) & (sg > 0)
+        if ok.sum() < 2:
+            return np.nan
+        ls, ks = np.log(sg[ok]), kgrid[ok]
+        order = np.argsort(ls)
+        return float(np.clip(np.interp(math.log(target[i]), ls[order], ks[order]), *KAPPA_RANGE))
+
+    k_sweep = np.array([from_sweep(i) for i in range(n_targets)])
+    sig_sweep = verify([(a, k if np.isfinite(k) else 0.0, t) for a, k, t in zip(A, k_sweep, T)], verify_steps)
+    sweep_ok = hit(sig_sweep, target)
+    sweep_runs = np.full(n_targets, len(kgrid) + 1.0)
+
+    # secant from Eq. (28): sigma_0 (counted), kappa_1 = 1 - sigma*/sigma_0, then secant updates
+    sec_runs = np.ones(n_targets)
+    sec_ok = np.zeros(n_targets, bool)
+    k_prev = np.zeros(n_targets)
+    s_prev = sigma0.copy()
+    k_cur = np.clip(1.0 - target / sigma0, *KAPPA_RANGE)
+    for it in range(3):
+        todo = valid & ~sec_ok
+        if not todo.any():
+            break
+        idx = np.where(todo)[0]
+        sg = verify([(A[i], k_cur[i], T[i]) for i in idx], verify_steps)
+        for j, i in enumerate(idx):
+            sec_runs[i] += 1
+            if hit(sg[j], target[i]):
+                sec_ok[i] = True
+            elif np.isfinite(sg[j]) and sg[j] != s_prev[i]:
+                k_new = k_cur[i] + (target[i] - sg[j]) * (k_cur[i] - k_prev[i]) / (sg[j] - s_prev[i])
+                k_prev[i], s_prev[i] = k_cur[i], sg[j]
+                k_cur[i] = float(np.clip(k_new, *KAPPA_RANGE))
+    sec_runs[~sec_ok] += sweep_runs[~sec_ok]  # fall back to the sweep
+
+    # surrogate: invert, verify once; fall back to the sweep if the check misses
+    k_sur = sur.invert_kappa(A, T, target)
+    sig_sur = verify([(a, k, t) for a, k, t in zip(A, k_sur, T)], verify_steps)
+    sur_ok = hit(sig_sur, target)
+    sur_runs = np.where(sur_ok, 1.0, 1.0 + sweep_runs)
+    sur_final_ok = sur_ok | sweep_ok
+
+    def stats(runs, ok):
+        m = valid
+        return dict(mean_runs=float(runs[m].mean()), success=float(ok[m].mean()),
+                    first_try_success=None)
+
+    rep = dict(
+        config=dict(seed=seed, n_targets=n_targets, train_batches=train_batches, domains=domains,
+                    train_steps=train_steps, verify_steps=verify_steps, side=list(side),
+                    verify_lattice=200, verify_radius=40, tolerance=TOLERANCE),
+        training=dict(samples=int(len(X)), outside_model_range=int(bad),
+                      loss_first=float(loss[0]), loss_last=float(loss[-1])),
+        targets_valid=int(valid.sum()),
+        surrogate=dict(stats(sur_runs, sur_final_ok), first_try_success=float(sur_ok[valid].mean()),
+                       median_abs_error=float(np.nanmedian(np.abs(sig_sur[valid] / target[valid] - 1)))),
+        plain_sweep=dict(stats(sweep_runs, sweep_ok),
+                         median_abs_error=float(np.nanmedian(np.abs(sig_sweep[valid] / target[valid] - 1)))),
+        secant_eq28=dict(stats(sec_runs, sec_ok | sweep_ok)),
+        seconds=time.time() - t_start,
+    )
+    return rep
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--out", default="surrogate_report.json")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--targets", type=int, default=64)
+    ap.add_argument("--train-batches", type=int, default=2)
+    ap.add_argument("--train-steps", type=int, default=20000)
+    ap.add_argument("--verify-steps", type=int, default=20000)
+    ap.add_argument("--iters", type=int, default=4000)
+    a = ap.parse_args()
+    rep = study(seed=a.seed, n_targets=a.targets, train_batches=a.train_batches,
+                train_steps=a.train_steps, verify_steps=a.verify_steps, iters=a.iters,
+                log=lambda m: print(m, flush=True))
+    with open(a.out, "w") as f:
+        json.dump(rep, f, indent=1)
+    print(json.dumps(rep), flush=True)
+
+
+if __name__ == "__main__":
+    main()
