@@ -92,6 +92,12 @@ typedef struct {
   double G;           /* interaction strength, < 0; results do not depend on it     */
   double s_e, s_eps, s_q, s_nu; /* MRT rates 1/tau of Eq. (2), each in (0, 2);
                                    s_rho and s_j do not enter (conserved moments)   */
+  /* Density-dependent shear viscosity (Sec. 4.2 gives gas and liquid values):
+   * with nu_gas > 0, each cell uses s_nu = 1 / (3 nu + 1/2) with
+   * nu = nu_gas + f (nu_liquid - nu_gas), f = (rho - rho_gas) / (rho_liquid - rho_gas)
+   * clamped to [0, 1], in place of the constant s_nu (also in the C source).
+   * nu_gas = 0 (default) keeps the constant s_nu. */
+  double nu_gas, nu_liquid, rho_gas, rho_liquid;
 } lbm_params;
 
 /* FP64 observables of the current state (Sec. 3.1.1, Eq. 22).
@@ -116,7 +122,8 @@ typedef struct {
 typedef struct lbm_ctx lbm_ctx;
 
 /* Fills *p with: 64 x 64, CS (a=1, b=4, R=1), K=1, T/Tc=0.8, A=-0.5,
- * kappa=0, G=-1, s_e=s_eps=s_nu=1, s_q=8/7, FP64.  Returns LBM_EINVAL on NULL. */
+ * kappa=0, G=-1, s_e=s_eps=s_nu=1, s_q=8/7, constant viscosity, FP64.
+ * Returns LBM_EINVAL on NULL. */
 lbm_status lbm_params_default(lbm_params* p);
 
 /* Critical temperature of the EOS in *p (K does not change it); *Tc receives it.

@@ -13,7 +13,7 @@ TEST INFRASTRUCTURE ONLY.  The product path never imports this package: only
 
 A physical configuration is a plain dict with keys
 ``nx, ny, eos ('ideal'|'cs'|'vdw'|'pr'), a, b, R, omega_pr, K, T_over_Tc, A,
-kappa, G, s_e, s_eps, s_q, s_nu``.  Missing keys take the defaults in
+kappa, G, s_e, s_eps, s_q, s_nu, nu_gas, nu_liquid, rho_gas, rho_liquid``.  Missing keys take the defaults in
 :data:`DEFAULTS`.
 """
 from __future__ import annotations
@@ -38,7 +38,8 @@ EOS_CONSTANTS = {
     "pr": dict(a=2.0 / 49.0, b=2.0 / 21.0, R=1.0),
 }
 DEFAULTS = dict(eos="cs", K=1.0, T_over_Tc=0.8, A=-0.5, kappa=0.0, G=-1.0, omega_pr=0.344,
-                s_e=1.0, s_eps=1.0, s_q=8.0 / 7.0, s_nu=1.0)
+                s_e=1.0, s_eps=1.0, s_q=8.0 / 7.0, s_nu=1.0, nu_gas=0.0, nu_liquid=0.0,
+                rho_gas=0.0, rho_liquid=0.0)
 
 # lattice velocities, used only to move between storage orders
 EX = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1])
@@ -63,7 +64,9 @@ class _Params(ctypes.Structure):
                 ("T", ctypes.c_double), ("Tc", ctypes.c_double),
                 ("A", ctypes.c_double), ("kappa", ctypes.c_double), ("G", ctypes.c_double),
                 ("s_rho", ctypes.c_double), ("s_e", ctypes.c_double), ("s_eps", ctypes.c_double),
-                ("s_j", ctypes.c_double), ("s_q", ctypes.c_double), ("s_nu", ctypes.c_double)]
+                ("s_j", ctypes.c_double), ("s_q", ctypes.c_double), ("s_nu", ctypes.c_double),
+                ("nu_gas", ctypes.c_double), ("nu_liquid", ctypes.c_double),
+                ("rho_gas", ctypes.c_double), ("rho_liquid", ctypes.c_double)]
 
 
 _lib = None
@@ -134,7 +137,8 @@ class Oracle:
         self.p = _Params(self.nx, self.ny, EOS_CODE[c["eos"]], int(nthreads),
                          c["a"], c["b"], c["R"], c["omega_pr"], c["K"], T, Tc,
                          c["A"], c["kappa"], c["G"],
-                         1.0, c["s_e"], c["s_eps"], 1.0, c["s_q"], c["s_nu"])
+                         1.0, c["s_e"], c["s_eps"], 1.0, c["s_q"], c["s_nu"],
+                         c["nu_gas"], c["nu_liquid"], c["rho_gas"], c["rho_liquid"])
         self.f = np.zeros((self.ny, self.nx, 9))
         self.steps = 0
         self.n_domain = 0

@@ -53,6 +53,9 @@ typedef struct {
   double Tc;     /* critical temperature (PR alpha(T) only) */
   double A, kappa, G;
   double s_rho, s_e, s_eps, s_j, s_q, s_nu;
+  /* nu_gas > 0: shear rate from nu(rho), linear in rho between rho_gas and
+   * rho_liquid (clamped), s_nu = 1 / (3 nu + 1/2) (Sec. 4.2) */
+  double nu_gas, nu_liquid, rho_gas, rho_liquid;
 } orc_params;
 
 /* -------------------------------------------------------------------------
@@ -204,9 +207,17 @@ static void collide(const orc_params *p, const double *M, const double *Minv, co
   double vF = vx * Fx + vy * Fy;
   double S[9] = {0.0, 6.0 * vF, -6.0 * vF, Fx, -Fx, Fy, -Fy,
                  2.0 * (vx * Fx - vy * Fy), vx * Fy + vy * Fx};
-  double s[9] = {p->s_rho, p->s_e, p->s_eps, p->s_j, p->s_q, p->s_j, p->s_q, p->s_nu, p->s_nu};
+  double s_nu = p->s_nu;
+  if (p->nu_gas > 0.0) {
+    double frac = (rho - p->rho_gas) / (p->rho_liquid - p->rho_gas);
+    if (frac < 0.0) frac = 0.0;
+    if (frac > 1.0) frac = 1.0;
+    double nu = p->nu_gas + frac * (p->nu_liquid - p->nu_gas);
+    s_nu = 1.0 / (3.0 * nu + 0.5);
+  }
+  double s[9] = {p->s_rho, p->s_e, p->s_eps, p->s_j, p->s_q, p->s_j, p->s_q, s_nu, s_nu};
   double C[9] = {0.0, 1.5 * p->s_e * (Qxx + Qyy), 0.0, 0.0, 0.0, 0.0, 0.0,
-                 -p->s_nu * (Qxx - Qyy), -p->s_nu * Qxy};
+                 -s_nu * (Qxx - Qyy), -s_nu * Qxy};
   double ms[9];
   for (int k = 0; k < 9; ++k)
     ms[k] = m[k] - s[k] * (m[k] - meq[k]) + (1.0 - 0.5 * s[k]) * S[k] + C[k];

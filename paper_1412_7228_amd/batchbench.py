@@ -1,0 +1,80 @@
+"""Throughput of the batched engine on the uneven droplet batch.
+
+256 independent Laplace droplets, square domains with side uniform in
+{64..512}, R = u * side with u ~ U[0.15, 0.35], T/Tc ~ U[0.6, 0.85],
+kappa ~ U[0, 0.8], A ~ U[-0.7, -0.3] (seeded), FP32, CS EOS.  Times both
+launch modes (one persistent launch per call, or one launch per step in HIP
+graphs) with HIP events on the batch's stream and prints one JSON line:
+MLUPS over all domains, the launch shapes, and how many domains stayed
+two-phase.
+
+    python -m paper_1412_7228_amd.batchbench [--steps 20000] [--domains 256]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import time
+
+import numpy as np
+
+from . import autotune, inputs, laplace, lbm
+
+
+def build(domains: int, seed: int, precision: str = "fp32"):
+    draws = inputs.batch_draws(domains, seed)
+    cases = [dict(n=d["nx"], R=d["R"], T_over_Tc=d["T_over_Tc"], A=d["A"], kappa=d["kappa"],
+                  seed=d["seed"]) for d in draws]
+    cfgs = [laplace.case_config(c, precision) for c in cases]
+    b = lbm.Batch(cfgs)
+    for i, (c, cfg) in enumerate(zip(cases, cfgs)):
+        b.init_field(i, laplace.initial_density(c, cfg))
+    cells = sum(c["n"] * c["n"] for c in cases)
+    return b, cases, cells
+
+
+def time_mode(b, mode, tile, steps):
+    import torch
+
+    b.set_launch(mode, *tile)
+    b.step(10)
+    b.sync()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(b.stream)
+    b.step(steps)
+    e1.record(b.stream)
+    b.sync()
+    return e0.elapsed_time(e1)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--domains", type=int, default=256)
+    ap.add_argument("--seed", type=int, default=3)
+    ap.add_argument("--tune", action="store_true", help="run the autotuner first")
+    a = ap.parse_args()
+    t0 = time.time()
+    b, cases, cells = build(a.domains, a.seed)
+    print(f"[batch] {a.domains} domains, {cells} cells, setup {time.time() - t0:.1f} s", flush=True)
+    tuned = None
+    if a.tune:
+        tuned = autotune.tune_batch(b, steps=20, use_cache=False)
+        print(f"[batch] autotune {tuned}", flush=True)
+    res = {}
+    for mode, tile in (("per_step", (64, 32)), ("persistent", (64, 32))):
+        ms = time_mode(b, mode, tile, a.steps)
+        res[mode] = dict(ms=ms, mlups=cells * a.steps / (ms * 1e-3) / 1e6, tile=list(tile),
+                         grid=b.launch["grid"], ntiles=b.launch["ntiles"])
+        print(f"[batch] {mode} {res[mode]}", flush=True)
+    obs = b.observables()
+    ok = sum(1 for c, o in zip(cases, obs) if o["n_nonfinite"] == 0 and o["rho_in"] > 1.5 * o["rho_out"] > 0)
+    line = dict(metric="MLUPS of the uneven droplet batch (FP32)", domains=a.domains, cells=cells,
+                steps=a.steps + 10, timed_steps=a.steps, modes=res, two_phase_domains=ok,
+                autotune=tuned, seconds=time.time() - t0)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -238,6 +238,7 @@ lbm_status model_of(const lbm_params& p, ModelConsts* m) {
   m->G = p.eos == LBM_EOS_IDEAL ? -1.0 : p.G;
   m->A = p.A; m->kappa = p.kappa;
   m->s_e = p.s_e; m->s_eps = p.s_eps; m->s_q = p.s_q; m->s_nu = p.s_nu;
+  m->nu_gas = p.nu_gas; m->nu_liquid = p.nu_liquid; m->rho_gas = p.rho_gas; m->rho_liquid = p.rho_liquid;
   m->T = 0.0;
   m->aalpha = p.a;
   if (p.eos != LBM_EOS_IDEAL) {
@@ -266,6 +267,10 @@ lbm_status validate(const lbm_params* p) {
   for (double s : rates)
     if (!(s > 0.0 && s < 2.0)) return fail(LBM_EINVAL, "relaxation rate %g outside (0, 2)", s);
   if (!std::isfinite(p->A) || !std::isfinite(p->kappa)) return fail(LBM_EINVAL, "A or kappa not finite");
+  if (p->nu_gas != 0.0) {
+    if (!(p->nu_gas > 0.0 && p->nu_liquid > 0.0 && p->rho_liquid > p->rho_gas && p->rho_gas >= 0.0))
+      return fail(LBM_EINVAL, "variable viscosity needs nu_gas, nu_liquid > 0 and rho_liquid > rho_gas >= 0");
+  }
   if (p->eos != LBM_EOS_IDEAL) {
     if (!(p->G < 0.0)) return fail(LBM_EINVAL, "G must be negative (got %g)", p->G);
     if (!(p->a > 0.0 && p->b > 0.0 && p->R > 0.0 && p->K > 0.0))

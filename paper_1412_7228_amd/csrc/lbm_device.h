@@ -36,6 +36,8 @@ struct DevC {
   T s_e, s_eps, s_q, s_nu;
   T h_e, h_eps, h_q, h_nu;  // 1 - s/2
   T c_e;                    // 1.5 s_e   (first non-zero entry of C, Eq. 26)
+  int var_nu;               // density-dependent shear viscosity
+  T nu_g, dnu, rho_g, inv_drho;
 };
 
 template <typename T>
@@ -59,6 +61,11 @@ inline DevC<T> make_devc(const ModelConsts& m) {
   c.h_q = T(1.0 - 0.5 * m.s_q);
   c.h_nu = T(1.0 - 0.5 * m.s_nu);
   c.c_e = T(1.5 * m.s_e);
+  c.var_nu = m.nu_gas > 0.0 ? 1 : 0;
+  c.nu_g = T(m.nu_gas);
+  c.dnu = T(m.nu_liquid - m.nu_gas);
+  c.rho_g = T(m.rho_gas);
+  c.inv_drho = T(m.nu_gas > 0.0 ? 1.0 / (m.rho_liquid - m.rho_gas) : 0.0);
   return c;
 }
 
@@ -134,6 +141,15 @@ __device__ __forceinline__ void collide_cell(const T (&g)[9], T rho, const T (&U
   const T pxx = a13 - a24;
   const T pxy = (g[5] + g[7]) - (g[6] + g[8]);
 
+  // ---- shear rate: constant, or from the density-dependent viscosity
+  T s_nu = c.s_nu, h_nu = c.h_nu;
+  if (c.var_nu) {
+    T fr = (rho - c.rho_g) * c.inv_drho;
+    fr = fr < T(0) ? T(0) : (fr > T(1) ? T(1) : fr);
+    s_nu = rcp_(T(3) * (c.nu_g + fr * c.dnu) + T(0.5));
+    h_nu = T(1) - T(0.5) * s_nu;
+  }
+
   // ---- velocity v = (j + F/2)/rho and the collision of Eq. (25)
   const T mx = jx + T(0.5) * Fx, my = jy + T(0.5) * Fy;  // rho v
   const T ir = rcp_(rho);
@@ -145,9 +161,9 @@ __device__ __forceinline__ void collide_cell(const T (&g)[9], T rho, const T (&U
   const T jxs = jx + Fx, jys = jy + Fy;
   const T qxs = qx - c.s_q * (qx + mx) - c.h_q * Fx;
   const T qys = qy - c.s_q * (qy + my) - c.h_q * Fy;
-  const T pxxs = pxx - c.s_nu * (pxx - (mx * vx - my * vy)) +
-                 c.h_nu * (T(2) * (vx * Fx - vy * Fy)) - c.s_nu * (Qxx - Qyy);
-  const T pxys = pxy - c.s_nu * (pxy - mx * vy) + c.h_nu * (vx * Fy + vy * Fx) - c.s_nu * Qxy;
+  const T pxxs = pxx - s_nu * (pxx - (mx * vx - my * vy)) +
+                 h_nu * (T(2) * (vx * Fx - vy * Fy)) - s_nu * (Qxx - Qyy);
+  const T pxys = pxy - s_nu * (pxy - mx * vy) + h_nu * (vx * Fy + vy * Fx) - s_nu * Qxy;
 
   // ---- f* = M^{-1} m*, M^{-1} = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4)
   const T r9 = rho * (T(1) / T(9));

@@ -28,6 +28,7 @@ struct ModelConsts {
   double aalpha;            // Peng-Robinson a * alpha(T)
   double G, A, kappa;
   double s_e, s_eps, s_q, s_nu;
+  double nu_gas, nu_liquid, rho_gas, rho_liquid;  // nu_gas > 0: density-dependent s_nu
 };
 
 // Fused density/psi + force + Q + MRT collision + streaming, one time step:

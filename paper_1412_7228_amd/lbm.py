@@ -8,7 +8,8 @@ HIP device is present, constructing a :class:`Lattice` raises.
 
 Parameters are passed as a plain dict with keys ``nx, ny, eos ('ideal'|'cs'|
 'vdw'|'pr'), a, b, R, omega_pr, K, T_over_Tc, A, kappa, G, s_e, s_eps, s_q,
-s_nu, precision ('fp64'|'fp32')``; missing keys take :data:`DEFAULTS`.
+s_nu, nu_gas, nu_liquid, rho_gas, rho_liquid, precision ('fp64'|'fp32')``;
+missing keys take :data:`DEFAULTS`.
 """
 from __future__ import annotations
 
@@ -30,7 +31,8 @@ EOS_CONSTANTS = {
 PRECISION = {"fp64": 0, "fp32": 1}
 FIELDS = {"rho": 0, "ux": 1, "uy": 2, **{f"f{a}": 3 + a for a in range(9)}}
 DEFAULTS = dict(eos="cs", K=1.0, T_over_Tc=0.8, A=-0.5, kappa=0.0, G=-1.0, omega_pr=0.344,
-                s_e=1.0, s_eps=1.0, s_q=8.0 / 7.0, s_nu=1.0, precision="fp64")
+                s_e=1.0, s_eps=1.0, s_q=8.0 / 7.0, s_nu=1.0, nu_gas=0.0, nu_liquid=0.0,
+                rho_gas=0.0, rho_liquid=0.0, precision="fp64")
 
 STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EDEVICE",
           -4: "LBM_ENONFINITE", -5: "LBM_EDOMAIN", -6: "LBM_ESTATE"}
@@ -50,7 +52,9 @@ class Params(ctypes.Structure):
                 ("T_over_Tc", ctypes.c_double), ("A", ctypes.c_double),
                 ("kappa", ctypes.c_double), ("G", ctypes.c_double),
                 ("s_e", ctypes.c_double), ("s_eps", ctypes.c_double), ("s_q", ctypes.c_double),
-                ("s_nu", ctypes.c_double)]
+                ("s_nu", ctypes.c_double), ("nu_gas", ctypes.c_double),
+                ("nu_liquid", ctypes.c_double), ("rho_gas", ctypes.c_double),
+                ("rho_liquid", ctypes.c_double)]
 
 
 class Obs(ctypes.Structure):
@@ -154,7 +158,8 @@ def make_params(cfg: dict) -> Params:
                   float(c["a"]), float(c["b"]), float(c["R"]), float(c["omega_pr"]),
                   float(c["K"]), float(c["T_over_Tc"]), float(c["A"]), float(c["kappa"]),
                   float(c["G"]), float(c["s_e"]), float(c["s_eps"]), float(c["s_q"]),
-                  float(c["s_nu"]))
+                  float(c["s_nu"]), float(c["nu_gas"]), float(c["nu_liquid"]),
+                  float(c["rho_gas"]), float(c["rho_liquid"]))
 
 
 def critical_temperature(cfg: dict) -> float:

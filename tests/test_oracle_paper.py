@@ -97,3 +97,55 @@ def test_laplace_law_cs(oracle_mod, ncpu):
     sig = np.array(sig)
     assert (sig.max() - sig.min()) / sig.mean() < 0.03
     assert abs(sig.mean() / th.sigma_leading_order(e, 0.8 * Tc, -0.5) - 1) < 0.05
+
+
+def _anisotropy(rho):
+    """(Ixx - Iyy)/(Ixx + Iyy) of the excess density about its centre of mass."""
+    ny, nx = rho.shape
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    w = rho - rho.min()
+    cx, cy = (w * x).sum() / w.sum(), (w * y).sum() / w.sum()
+    return ((w * (x - cx) ** 2).sum() - (w * (y - cy) ** 2).sum()) / ((w * (x - cx) ** 2).sum() + (w * (y - cy) ** 2).sum())
+
+
+def _period_from_crossings(t, a):
+    """Mean period from the first four zero crossings of a about its late-time mean."""
+    am = np.asarray(a) - np.mean(a[len(a) // 2:])
+    zc = [t[i] - am[i] * (t[i + 1] - t[i]) / (am[i + 1] - am[i]) for i in range(len(am) - 1)
+          if am[i] * am[i + 1] < 0]
+    return 2.0 * (zc[3] - zc[0]) / 3.0
+
+
+def test_capillary_oscillation_period_eq30(oracle_mod, ncpu):
+    """Sec. 4.2: an elliptic drop (semi-axes 30, 27, 120^2, gas/liquid viscosity
+    0.2/0.1) oscillates with the period of Eq. (30) (2 pi outside the root),
+    T = 2 pi sqrt(rho_l R0^3 / (6 sigma)), R0 = sqrt(30 x 27), within the paper's
+    own error range (3.5 to 15.9 %); halving sigma with kappa = 0.5 lengthens it
+    by about sqrt(2)."""
+    e = th.carnahan_starling()
+    _, Tc = th.critical_point(e)
+    rv, rl = th.maxwell(e, 0.8 * Tc)
+    n = 120
+    R0 = np.sqrt(30 * 27)
+    periods = {}
+    for kappa, nsamp in ((0.0, 250), (0.5, 330)):
+        cfg = dict(nx=n, ny=n, eos="cs", T_over_Tc=0.8, A=-0.5, kappa=kappa, nu_gas=0.2,
+                   nu_liquid=0.1, rho_gas=rv, rho_liquid=rl)
+        o = oracle_mod.Oracle(cfg, nthreads=ncpu)
+        o.init_field(inputs.ellipse(n, n, 30, 27, rl, rv, W=5.0))
+        ts, aa = [], []
+        for k in range(nsamp):
+            o.run(40)
+            ts.append(o.steps)
+            aa.append(_anisotropy(o.fields()["rho"]))
+        period = _period_from_crossings(np.array(ts, float), np.array(aa))
+        d = oracle_mod.Oracle(cfg, nthreads=ncpu)
+        d.init_field(inputs.droplet(n, n, R0, rl, rv, W=5.0, noise=0.0))
+        d.run(8000)
+        ob = d.observables()
+        Tth = 2 * np.pi * np.sqrt(ob["rho_in"] * R0 ** 3 / (6 * ob["sigma"]))
+        assert abs(period / Tth - 1) < 0.159, (kappa, period, Tth)
+        periods[kappa] = (period, ob["sigma"])
+    ratio = periods[0.5][0] / periods[0.0][0]
+    expect = np.sqrt(periods[0.0][1] / periods[0.5][1])
+    assert abs(ratio / expect - 1) < 0.1
