@@ -181,27 +181,35 @@ def spinodal(eos: EOS, T: float, Tc: float | None = None) -> tuple[float, float]
 def maxwell(eos: EOS, T: float, Tc: float | None = None) -> tuple[float, float]:
     """Coexisting (rho_v, rho_l): equal pressure and equal area in the specific volume.
 
-    Equal area is written as  int_{rho_v}^{rho_l} p/rho^2 drho = p_s (1/rho_v - 1/rho_l).
+    For a trial pressure P between the spinodal pressures, rho_v(P) and rho_l(P)
+    are the outer roots of p(rho) = P, and the equal-area rule reads
+    A(P) = int_{1/rho_l}^{1/rho_v} (p(1/v) - P) dv = 0.  A(P) falls
+    monotonically with P, so the saturation pressure is a bracketed 1-D root.
     """
     s_lo, s_hi = spinodal(eos, T, Tc)
     p = lambda r: float(eos._raw(r, T, Tc)[0])
+    rho_hi = 0.999 * (4.0 / eos.b if eos.kind == "cs" else 1.0 / eos.b)
+    p_top = p(s_lo)                      # local maximum of the loop
+    p_bot = max(p(s_hi), 1e-12 * p_top)  # local minimum (the vapour needs p > 0)
 
-    def res(v):
-        rv, rl = v
-        ps = p(rv)
-        area = integrate.quad(lambda r: p(r) / r**2, rv, rl, epsabs=1e-15, epsrel=1e-13, limit=200)[0]
-        return [p(rl) - ps, area - ps * (1.0 / rv - 1.0 / rl)]
+    def roots(P):
+        rv = optimize.brentq(lambda r: p(r) - P, 1e-300 if P > 0 else 1e-12, s_lo, xtol=1e-300, rtol=1e-15, maxiter=500)
+        rl = optimize.brentq(lambda r: p(r) - P, s_hi, rho_hi, xtol=1e-300, rtol=1e-15, maxiter=500)
+        return rv, rl
 
-    # start: vapour well below the low spinodal, liquid above the high one
-    best = None
-    for fv, fl in ((0.3, 1.3), (0.1, 1.5), (0.5, 1.2), (0.05, 1.8)):
-        sol, info, ier, _ = optimize.fsolve(res, [s_lo * fv, s_hi * fl], xtol=1e-14, full_output=True)
-        if ier == 1 and sol[0] < s_lo and sol[1] > s_hi and sol[0] > 0:
-            best = sol
-            break
-    if best is None:
-        raise RuntimeError("Maxwell construction did not converge")
-    return float(best[0]), float(best[1])
+    def area(P):
+        # in the specific volume v = 1/rho the integrand p(1/v) - P is bounded
+        rv, rl = roots(P)
+        vv, vl = 1.0 / rv, 1.0 / rl
+        return integrate.quad(lambda v: p(1.0 / v) - P, vl, vv, points=[1.0 / s_hi, 1.0 / s_lo],
+                              epsabs=1e-13 * P * (vv - vl), epsrel=1e-13, limit=400)[0]
+
+    lo, hi = p_bot * (1 + 1e-12), p_top * (1 - 1e-12)
+    if not (area(lo) > 0 > area(hi)):
+        raise RuntimeError("Maxwell construction: no equal-area pressure between the spinodals")
+    P = optimize.brentq(area, lo, hi, xtol=1e-300, rtol=1e-15, maxiter=500)
+    rv, rl = roots(P)
+    return float(rv), float(rl)
 
 
 # --------------------------------------------------------------------------

@@ -58,7 +58,8 @@ def _coexistence_by_chemical_potential(kind, T):
     return p, mu
 
 
-@pytest.mark.parametrize("kind,tr", [("vdw", 0.9), ("cs", 0.8), ("cs", 0.7), ("cs", 0.6)])
+@pytest.mark.parametrize("kind,tr", [("vdw", 0.9), ("vdw", 0.76), ("vdw", 0.78), ("vdw", 0.82),
+                                     ("vdw", 0.6), ("cs", 0.8), ("cs", 0.7), ("cs", 0.6), ("cs", 0.95)])
 def test_maxwell_matches_chemical_potential_equality(kind, tr):
     e = th.vdw(0.3) if kind == "vdw" else th.carnahan_starling()
     _, Tc = th.critical_point(e)
