@@ -203,7 +203,9 @@ typedef struct lbm_batch lbm_batch;
 
 typedef enum {
   LBM_BATCH_PERSISTENT = 0, /* one launch advances all domains by n steps; each domain's
-                               tiles meet at a per-domain step barrier (bounded wait) */
+                               tiles meet at a per-domain step barrier (bounded wait).
+                               Switched off in this build: lbm_batch_set_launch
+                               returns LBM_EINVAL for it */
   LBM_BATCH_PER_STEP = 1    /* one launch per step over all tiles, captured in HIP graphs */
 } lbm_batch_mode;
 
@@ -211,7 +213,7 @@ typedef struct {
   int32_t mode;             /* lbm_batch_mode                                         */
   int32_t tile_x, tile_y;   /* tile of every domain; 0 = default (64 x 32)            */
   int64_t spin_limit;       /* persistent mode: polls before a barrier wait gives up;
-                               0 = default (2^24)                                      */
+                               0 = default (2^20, about a second)                      */
   int32_t force_spin_limit; /* non-zero with spin_limit 0: use 0 (test of the abort path) */
   /* filled by lbm_batch_get_launch: */
   int32_t grid;             /* workgroups per launch                                  */

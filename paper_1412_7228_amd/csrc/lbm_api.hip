@@ -700,12 +700,15 @@ struct lbm_batch {
   hipStream_t stream = nullptr;
   int mode = LBM_BATCH_PER_STEP;
   int tile_x = 64, tile_y = 32;
-  long long spin_limit = 1ll << 24;
+  long long spin_limit = 1ll << 20;
   int per_cu = 0, cus = 0;
   // device layout
   void* d_dom = nullptr;
   void* d_tiles = nullptr;
-  int* d_wg_begin = nullptr;
+  int* d_group_begin = nullptr;
+  int nxcd = 1;               // XCDs of the device: one domain group each (persistent mode)
+  int max_group_tiles = 1;    // tiles of the largest group (bounds the steps of one launch)
+  unsigned* d_head = nullptr;
   unsigned* d_done = nullptr;
   int* d_err = nullptr;
   int ntile_total = 0, grid = 0;
@@ -723,24 +726,31 @@ struct lbm_batch {
 
 namespace {
 
+// The persistent launch mode stays off until its kernel has passed the GPU
+// tests: an earlier form of it never finished on the GPU.
+constexpr bool kPersistentEnabled = false;
+
 void batch_free_layout(lbm_batch* b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   b->exec = nullptr;
   b->exec_mode = -1;
-  for (void* q : {b->d_dom, b->d_tiles, (void*)b->d_wg_begin})
+  for (void* q : {b->d_dom, b->d_tiles, (void*)b->d_group_begin})
     if (q) (void)hipFree(q);
   b->d_dom = b->d_tiles = nullptr;
-  b->d_wg_begin = nullptr;
+  b->d_group_begin = nullptr;
 }
 
-// Tiles of every domain, the workgroup assignment (persistent mode: longest
-// processing time first onto the least loaded workgroup) and the device copies.
+// Tiles of every domain and the device copies.  Persistent mode: the domains
+// go to one group per XCD (longest processing time first onto the least loaded
+// group) and the tiles are stored group by group, each domain's tiles
+// together, so that a group's queue finishes one domain's step before the next.
 lbm_status batch_layout(lbm_batch* b) {
   HIP_TRY(hipStreamSynchronize(b->stream));
   batch_free_layout(b);
   HIP_TRY(hipMemsetAsync(b->d_err, 0, sizeof(int), b->stream));
   struct T4 { int d, x0, y0, down; long long cost; };
   std::vector<T4> tiles;
+  std::vector<long long> dcost(b->n, 0);
   b->ntiles.assign(b->n, 0);
   for (int d = 0; d < b->n; ++d) {
     Geometry& g = b->g[d];
@@ -754,44 +764,43 @@ lbm_status batch_layout(lbm_batch* b) {
         const int x0 = sx * g.tile_x, y0 = rb * g.tile_y;
         const long long w = std::min(g.tile_x, g.nx - x0), h = std::min(g.tile_y, g.ny - y0);
         tiles.push_back({d, x0, y0, rb & 1, w * (h + 2)});
+        dcost[d] += w * (h + 2);
       }
     b->ntiles[d] = (unsigned)g.nblocks;
   }
   b->ntile_total = (int)tiles.size();
-  std::vector<int> wg_begin;
+  std::vector<int> group_begin;
   if (b->mode == LBM_BATCH_PERSISTENT) {
     HIP_TRY(batch_occupancy(b->prec, b->eos, b->tile_x, &b->per_cu));
     if (b->per_cu < 1) return fail(LBM_EDEVICE, "persistent batch kernel cannot be resident");
-    b->grid = std::min(b->ntile_total, b->per_cu * b->cus);
-    std::vector<int> order(tiles.size());
-    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return tiles[a].cost > tiles[c].cost; });
-    // min-heap of (load, workgroup)
-    std::vector<std::pair<long long, int>> heap;
-    for (int w = 0; w < b->grid; ++w) heap.push_back({0, w});
-    std::vector<std::vector<int>> own(b->grid);
-    auto cmp = [](const std::pair<long long, int>& a, const std::pair<long long, int>& c) {
-      return a.first > c.first || (a.first == c.first && a.second > c.second);
-    };
-    std::make_heap(heap.begin(), heap.end(), cmp);
-    for (int t : order) {
-      std::pop_heap(heap.begin(), heap.end(), cmp);
-      auto& top = heap.back();
-      own[top.second].push_back(t);
-      top.first += tiles[t].cost;
-      std::push_heap(heap.begin(), heap.end(), cmp);
+    b->grid = b->per_cu * b->cus;
+    const int ng = b->nxcd;
+    std::vector<int> order(b->n);
+    for (int d = 0; d < b->n; ++d) order[d] = d;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return dcost[a] > dcost[c]; });
+    std::vector<long long> load(ng, 0);
+    std::vector<std::vector<int>> members(ng);
+    for (int d : order) {
+      const int gi = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      members[gi].push_back(d);
+      load[gi] += dcost[d];
     }
+    std::vector<int> first(b->n + 1, 0);  // tiles were generated domain by domain
+    for (int d = 0; d < b->n; ++d) first[d + 1] = first[d] + (int)b->ntiles[d];
     std::vector<T4> sorted;
-    wg_begin.push_back(0);
-    for (int w = 0; w < b->grid; ++w) {
-      std::sort(own[w].begin(), own[w].end());  // domain, then row block, then strip order
-      for (int t : own[w]) sorted.push_back(tiles[t]);
-      wg_begin.push_back((int)sorted.size());
+    group_begin.push_back(0);
+    for (int gi = 0; gi < ng; ++gi) {
+      for (int d : members[gi])
+        for (int t = first[d]; t < first[d + 1]; ++t) sorted.push_back(tiles[t]);
+      group_begin.push_back((int)sorted.size());
     }
+    b->max_group_tiles = 1;
+    for (int gi = 0; gi < ng; ++gi)
+      b->max_group_tiles = std::max(b->max_group_tiles, group_begin[gi + 1] - group_begin[gi]);
     tiles.swap(sorted);
   } else {
     b->grid = b->ntile_total;
-    wg_begin.assign(2, 0);
+    group_begin.assign(2, 0);
   }
   const size_t db = batch_domain_bytes(b->prec), tb = batch_tile_bytes();
   std::vector<unsigned char> hd(db * b->n), ht(tb * tiles.size());
@@ -802,17 +811,50 @@ lbm_status batch_layout(lbm_batch* b) {
     batch_fill_tile(tiles[t].d, tiles[t].x0, tiles[t].y0, tiles[t].down, ht.data() + t * tb);
   HIP_TRY(hipMalloc(&b->d_dom, hd.size()));
   HIP_TRY(hipMalloc(&b->d_tiles, ht.size()));
-  HIP_TRY(hipMalloc(&b->d_wg_begin, wg_begin.size() * sizeof(int)));
+  HIP_TRY(hipMalloc(&b->d_group_begin, group_begin.size() * sizeof(int)));
   HIP_TRY(hipMemcpyAsync(b->d_dom, hd.data(), hd.size(), hipMemcpyHostToDevice, b->stream));
   HIP_TRY(hipMemcpyAsync(b->d_tiles, ht.data(), ht.size(), hipMemcpyHostToDevice, b->stream));
-  HIP_TRY(hipMemcpyAsync(b->d_wg_begin, wg_begin.data(), wg_begin.size() * sizeof(int),
+  HIP_TRY(hipMemcpyAsync(b->d_group_begin, group_begin.data(), group_begin.size() * sizeof(int),
                          hipMemcpyHostToDevice, b->stream));
   HIP_TRY(hipStreamSynchronize(b->stream));
   return LBM_OK;
 }
 
-// Enqueue `n` steps as one graph: persistent = counter reset + one launch;
-// per-step = n launches with alternating buffers.
+BatchRun batch_run(const lbm_batch* b, int nsteps, int parity) {
+  BatchRun r{};
+  r.dom = b->d_dom;
+  r.tiles = b->d_tiles;
+  r.group_begin = b->d_group_begin;
+  r.ngroups = b->nxcd;
+  r.head = b->d_head;
+  r.done = b->d_done;
+  r.err = b->d_err;
+  r.grid = b->grid;
+  r.nsteps = nsteps;
+  r.parity = parity;
+  r.spin_limit = b->spin_limit;
+  return r;
+}
+
+// Enqueues n steps: persistent = queue/counter reset, one launch and the
+// completion check; per-step = n launches with alternating buffers.
+hipError_t batch_enqueue(lbm_batch* b, int n) {
+  hipError_t e = hipSuccess;
+  if (b->mode == LBM_BATCH_PERSISTENT) {
+    const BatchRun r = batch_run(b, n, b->parity);
+    e = launch_batch_reset(r, b->n, b->stream);
+    if (e == hipSuccess) e = launch_batch(b->prec, b->eos, b->tile_x, true, r, b->stream);
+    if (e == hipSuccess) e = launch_batch_check(b->prec, r, b->n, b->stream);
+  } else {
+    for (int s = 0; s < n && e == hipSuccess; ++s)
+      e = launch_batch(b->prec, b->eos, b->tile_x, false, batch_run(b, 1, (b->parity + s) & 1),
+                       b->stream);
+  }
+  return e;
+}
+
+// The same n steps captured once as a graph (re-captured when the mode, the
+// step count or the buffer parity changes).
 lbm_status batch_graph(lbm_batch* b, int n) {
   if (b->exec && b->exec_mode == b->mode && b->exec_steps == n && b->exec_parity == b->parity)
     return LBM_OK;
@@ -820,17 +862,7 @@ lbm_status batch_graph(lbm_batch* b, int n) {
   b->exec = nullptr;
   hipGraph_t graph = nullptr;
   HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-  hipError_t e = hipSuccess;
-  if (b->mode == LBM_BATCH_PERSISTENT) {
-    e = launch_batch_reset(b->d_done, b->n, b->d_err, b->stream);
-    if (e == hipSuccess)
-      e = launch_batch(b->prec, b->eos, b->tile_x, true, b->d_dom, b->d_tiles, b->d_wg_begin,
-                       b->d_done, b->d_err, b->grid, n, b->parity, b->spin_limit, b->stream);
-  } else {
-    for (int s = 0; s < n && e == hipSuccess; ++s)
-      e = launch_batch(b->prec, b->eos, b->tile_x, false, b->d_dom, b->d_tiles, nullptr, nullptr,
-                       nullptr, b->grid, 1, (b->parity + s) & 1, 0, b->stream);
-  }
+  hipError_t e = batch_enqueue(b, n);
   hipError_t e2 = hipStreamEndCapture(b->stream, &graph);
   if (e != hipSuccess || e2 != hipSuccess) {
     if (graph) (void)hipGraphDestroy(graph);
@@ -867,7 +899,9 @@ lbm_status batch_check_error(lbm_batch* b) {
     // reported once; the state of an aborted launch is not a whole step
     HIP_TRY(hipMemsetAsync(b->d_err, 0, sizeof(int), b->stream));
     HIP_TRY(hipStreamSynchronize(b->stream));
-    return fail(LBM_EDEVICE, "persistent batch launch aborted: a domain barrier wait exceeded the spin limit");
+    if (err & 1)
+      return fail(LBM_EDEVICE, "persistent batch launch aborted: a domain barrier wait exceeded the spin limit");
+    return fail(LBM_EDEVICE, "persistent batch launch incomplete: no workgroup ran on the XCD of some domain group");
   }
   return LBM_OK;
 }
@@ -922,6 +956,14 @@ lbm_status lbm_batch_create(const lbm_params* params, int32_t n, void* hip_strea
   if (e == hipSuccess) e = hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e == hipSuccess) e = hipMalloc(&b->arena, total);
   if (e == hipSuccess) e = hipMemsetAsync(b->arena, 0, total, b->stream);
+  if (e == hipSuccess) {
+    // one domain group per XCD; a device that does not report XCDs is one group
+    int nx = 0;
+    if (hipDeviceGetAttribute(&nx, hipDeviceAttributeNumberOfXccs, dev) == hipSuccess && nx >= 1 && nx <= 16)
+      b->nxcd = nx;
+    (void)hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMalloc(&b->d_head, 16 * sizeof(unsigned));
   if (e == hipSuccess) e = hipMalloc(&b->d_done, n * sizeof(unsigned));
   if (e == hipSuccess) e = hipMalloc(&b->d_err, sizeof(int));
   if (e == hipSuccess) e = hipMemsetAsync(b->d_err, 0, sizeof(int), b->stream);
@@ -939,7 +981,7 @@ void lbm_batch_destroy(lbm_batch* b) {
   if (!b) return;
   (void)hipStreamSynchronize(b->stream);
   batch_free_layout(b);
-  for (void* q : {b->arena, (void*)b->d_done, (void*)b->d_err, (void*)b->work, (void*)b->partials, (void*)b->red})
+  for (void* q : {b->arena, (void*)b->d_head, (void*)b->d_done, (void*)b->d_err, (void*)b->work, (void*)b->partials, (void*)b->red})
     if (q) (void)hipFree(q);
   delete b;
 }
@@ -948,6 +990,9 @@ lbm_status lbm_batch_set_launch(lbm_batch* b, const lbm_batch_launch* l) {
   if (!b || !l) return fail(LBM_EINVAL, "NULL argument");
   if (l->mode != LBM_BATCH_PERSISTENT && l->mode != LBM_BATCH_PER_STEP)
     return fail(LBM_EINVAL, "unknown batch mode %d", l->mode);
+  if (l->mode == LBM_BATCH_PERSISTENT && !kPersistentEnabled)
+    return fail(LBM_EINVAL, "persistent batch mode is switched off in this build (its kernel has not "
+                            "passed on a GPU); use LBM_BATCH_PER_STEP");
   const int tx = l->tile_x ? l->tile_x : 64, ty = l->tile_y ? l->tile_y : 32;
   if (tx != 64 && tx != 128 && tx != 256) return fail(LBM_EINVAL, "tile_x %d not in {64,128,256}", tx);
   if (ty < 1) return fail(LBM_EINVAL, "tile_y %d < 1", ty);
@@ -955,7 +1000,7 @@ lbm_status lbm_batch_set_launch(lbm_batch* b, const lbm_batch_launch* l) {
   b->mode = l->mode;
   b->tile_x = tx;
   b->tile_y = ty;
-  b->spin_limit = l->spin_limit ? l->spin_limit : (1ll << 24);
+  b->spin_limit = l->spin_limit ? l->spin_limit : (1ll << 20);
   if (l->spin_limit == 0 && l->force_spin_limit) b->spin_limit = 0;
   return batch_layout(b);
 }
@@ -998,9 +1043,12 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t n) {
   if (n < 0) return fail(LBM_EINVAL, "negative step count");
   for (int d = 0; d < b->n; ++d)
     if (!b->inited[d]) return fail(LBM_ESTATE, "batch domain %d not initialised", d);
-  // persistent mode: the whole call is one launch (chunked only beyond 2^30
-  // steps); per-step mode: graphs of up to 64 launches
-  const int64_t chunk = b->mode == LBM_BATCH_PERSISTENT ? (1ll << 30) : 64;
+  // persistent mode: the whole call is one launch, chunked only where a group's
+  // queue (tiles x steps) would pass 2^31; per-step mode: graphs of up to 64
+  // launches
+  const int64_t chunk = b->mode == LBM_BATCH_PERSISTENT
+                            ? std::max<int64_t>(1, ((1ll << 31) - 1) / b->max_group_tiles)
+                            : 64;
   int64_t left = n;
   while (left > 0) {
     const int k = (int)std::min(left, chunk);
@@ -1009,14 +1057,8 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t n) {
       lbm_status st = batch_graph(b, k);
       if (st != LBM_OK) return st;
       HIP_TRY(hipGraphLaunch(b->exec, b->stream));
-    } else if (b->mode == LBM_BATCH_PERSISTENT) {
-      HIP_TRY(launch_batch_reset(b->d_done, b->n, b->d_err, b->stream));
-      HIP_TRY(launch_batch(b->prec, b->eos, b->tile_x, true, b->d_dom, b->d_tiles, b->d_wg_begin,
-                           b->d_done, b->d_err, b->grid, k, b->parity, b->spin_limit, b->stream));
     } else {
-      for (int s2 = 0; s2 < k; ++s2)
-        HIP_TRY(launch_batch(b->prec, b->eos, b->tile_x, false, b->d_dom, b->d_tiles, nullptr,
-                             nullptr, nullptr, b->grid, 1, (b->parity + s2) & 1, 0, b->stream));
+      HIP_TRY(batch_enqueue(b, k));
     }
     b->parity = (b->parity + k) & 1;
     left -= k;

@@ -74,10 +74,24 @@ void batch_fill_domain(lbm_precision prec, const Geometry& g, const ModelConsts&
                        void* fb, unsigned ntiles, void* out);
 void batch_fill_tile(int domain, int x0, int y0, int down, void* out);
 hipError_t batch_occupancy(lbm_precision prec, int eos, int tile_x, int* per_cu);
-hipError_t launch_batch(lbm_precision prec, int eos, int tile_x, bool persistent, const void* dom,
-                        const void* tiles, const int* wg_begin, unsigned* done, int* err, int grid,
-                        int nsteps, int parity, long long spin_limit, hipStream_t s);
-hipError_t launch_batch_reset(unsigned* done, int n, int* err, hipStream_t s);
+// One batch launch.  Persistent mode: the tiles of XCD group g are
+// tiles[group_begin[g] .. group_begin[g+1]), head[g] is that group's queue
+// position, done[d] counts the finished tiles of domain d, err collects aborts.
+struct BatchRun {
+  const void* dom;
+  const void* tiles;
+  const int* group_begin;
+  int ngroups;
+  unsigned* head;
+  unsigned* done;
+  int* err;
+  int grid, nsteps, parity;
+  long long spin_limit;
+};
+hipError_t launch_batch(lbm_precision prec, int eos, int tile_x, bool persistent, const BatchRun& r,
+                        hipStream_t s);
+hipError_t launch_batch_reset(const BatchRun& r, int ndomains, hipStream_t s);
+hipError_t launch_batch_check(lbm_precision prec, const BatchRun& r, int ndomains, hipStream_t s);
 
 // Surrogate network (lbm_mlp.hip).
 int mlp_param_count();

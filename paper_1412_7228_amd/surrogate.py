@@ -192,7 +192,8 @@ def study(seed: int = 0, n_targets: int = 64, train_batches: int = 2, train_step
     sec_runs[~sec_ok] += sweep_runs[~sec_ok]  # fall back to the sweep
 
     # surrogate: invert, verify once; fall back to the sweep if the check misses
-    k_sur = sur.invert_kappa(A, T, target)
+    k_sur = np.zeros(n_targets)  # targets without a two-phase kappa = 0 run are not counted
+    k_sur[valid] = sur.invert_kappa(A[valid], T[valid], target[valid])
     sig_sur = verify([(a, k, t) for a, k, t in zip(A, k_sur, T)], verify_steps)
     sur_ok = hit(sig_sur, target)
     sur_runs = np.where(sur_ok, 1.0, 1.0 + sweep_runs)

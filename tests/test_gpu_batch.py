@@ -1,6 +1,11 @@
 """The batched engine (lbm_batch_*): every domain of an uneven batch must equal the
-same lattice run alone (bitwise: same per-tile arithmetic) in both launch modes, and
-the oracle; a forced barrier timeout must end the launch with an error, not a hang."""
+same lattice run alone (bitwise: same per-tile arithmetic) and the oracle.
+
+The persistent launch mode is switched off in the library (set_launch rejects it):
+an earlier form of its kernel never finished on the GPU, because a loop whose end
+depended on thread 0 was compiled into an inner loop that the other lanes of the
+wave never left.  Its tests stay here, skipped, until the restructured kernel has
+run on a GPU."""
 import sys
 
 import numpy as np
@@ -10,6 +15,10 @@ from oracle import thermo as th
 from paper_1412_7228_amd import inputs
 
 pytestmark = pytest.mark.gpu
+
+PERSISTENT_OFF = ("persistent batch mode is switched off: an earlier form of its kernel hung "
+                  "on the GPU (lane-divergent inner loop); the restructured kernel has not run "
+                  "on a GPU yet")
 
 
 def say(msg):
@@ -53,7 +62,8 @@ def _rho0(i, d):
     return inputs.droplet(d["nx"], d["ny"], d["R"], rl, rv, W=4.0, noise=1e-2, seed=i)
 
 
-@pytest.mark.parametrize("mode", ["per_step", "persistent"])
+@pytest.mark.parametrize("mode", ["per_step",
+                                  pytest.param("persistent", marks=pytest.mark.skip(reason=PERSISTENT_OFF))])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_batch_equals_single_lattices(lbm, mode, precision):
     say(f"batch {mode} {precision}")
@@ -73,10 +83,10 @@ def test_batch_equals_single_lattices(lbm, mode, precision):
 
 
 def test_batch_matches_oracle_fp64(lbm, oracle_mod):
-    say("batch persistent vs oracle")
+    say("batch per-step vs oracle")
     cfgs = _cfgs("fp64")
     b = lbm.Batch(cfgs)
-    b.set_launch("persistent", 64, 8)
+    b.set_launch("per_step", 64, 8)
     for i, d in enumerate(DOMAINS):
         b.init_field(i, _rho0(i, d))
     b.step(40)
@@ -92,6 +102,7 @@ def test_batch_matches_oracle_fp64(lbm, oracle_mod):
         assert obs[i]["step"] == 40
 
 
+@pytest.mark.skip(reason=PERSISTENT_OFF)
 def test_persistent_barrier_timeout_aborts_cleanly(lbm):
     """Spin limit 0: any tile that must wait gives up, sets the error flag and every
     workgroup leaves; the launch ends and the host sees LBM_EDEVICE."""
@@ -115,3 +126,48 @@ def test_batch_rejects_mixed_eos(lbm):
     say("batch mixed eos")
     with pytest.raises(lbm.LBMError):
         lbm.Batch([dict(nx=16, ny=16, eos="cs"), dict(nx=16, ny=16, eos="vdw", K=0.3, T_over_Tc=0.9)])
+
+
+@pytest.mark.skip(reason=PERSISTENT_OFF)
+@pytest.mark.parametrize("tile", [(64, 8), (128, 16), (256, 8)])
+def test_persistent_many_domains_equals_per_step(lbm, tile):
+    """48 uneven domains (more than one per XCD group), several launches of the
+    persistent engine, multi-wave workgroups: bitwise equal to per-step launches."""
+    say(f"batch persistent many domains tile {tile}")
+    rng = np.random.default_rng(5)
+    e = th.carnahan_starling()
+    _, Tc = th.critical_point(e)
+    cfgs, rhos = [], []
+    for i in range(48):
+        nx, ny = int(rng.integers(12, 160)), int(rng.integers(12, 160))
+        T = float(rng.uniform(0.7, 0.85))
+        rv, rl = th.maxwell(e, T * Tc)
+        cfgs.append(dict(nx=nx, ny=ny, eos="cs", precision="fp32", T_over_Tc=T,
+                         A=float(rng.uniform(-0.7, -0.3)), kappa=float(rng.uniform(0.0, 0.8))))
+        R = max(1.0, 0.3 * min(nx, ny))
+        rhos.append(inputs.droplet(nx, ny, R, rl, rv, W=4.0, noise=1e-2, seed=100 + i))
+    runs = {}
+    for mode in ("persistent", "per_step"):
+        b = lbm.Batch(cfgs)
+        b.set_launch(mode, *tile)
+        for i, r in enumerate(rhos):
+            b.init_field(i, r)
+        for k in (1, 99, 200):
+            b.step(k)
+        b.sync()
+        runs[mode] = [b.f_soa(i) for i in range(len(cfgs))]
+    for i in range(len(cfgs)):
+        assert np.array_equal(runs["persistent"][i], runs["per_step"][i], equal_nan=True), i
+
+
+def test_persistent_mode_is_rejected_while_switched_off(lbm):
+    say("batch persistent mode rejected")
+    b = lbm.Batch(_cfgs("fp32")[:2])
+    with pytest.raises(lbm.LBMError) as ei:
+        b.set_launch("persistent", 64, 16)
+    assert ei.value.status == -1
+    # the batch keeps its per-step plan and still runs
+    for i, d in enumerate(DOMAINS[:2]):
+        b.init_field(i, _rho0(i, d))
+    b.step(3)
+    b.sync()
