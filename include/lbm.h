@@ -113,10 +113,16 @@ typedef struct {
 } lbm_obs;
 
 /* Launch shape of the fused step kernel: a workgroup owns a strip of
- * tile_x columns and marches over tile_y rows. tile_x in {64, 128, 256};
- * tile_y >= 1.  0 selects the library default for the lattice. */
+ * tile_x columns and marches over tile_y rows.
+ *   steps_per_pass = 1: one time step per launch; tile_x in {64, 128, 256}.
+ *   steps_per_pass = 2: two time steps per launch (each pass reads and writes
+ *     the state once; bitwise the same states as single steps); tile_x in
+ *     {128, 256}, of which tile_x - 6 columns are stored per strip.  An odd
+ *     step count ends with one single-step launch of the default shape.
+ * tile_y >= 1.  0 in any field selects the library default for the lattice. */
 typedef struct {
   int32_t tile_x, tile_y;
+  int32_t steps_per_pass;
 } lbm_launch;
 
 typedef struct lbm_ctx lbm_ctx;

@@ -297,7 +297,9 @@ size_t elem_size(const lbm_params& p) { return p.precision == LBM_FP32 ? 4 : 8; 
 struct lbm_ctx {
   lbm_params p;
   ModelConsts m;
-  Geometry g;
+  Geometry g;   // single-step kernel (and the lattice's layout for read-out)
+  Geometry g2;  // two-step kernel
+  int fuse;     // steps per pass: 1 or 2
   size_t buf_bytes;
   void* buf[2];
   bool own_buf;
@@ -314,17 +316,28 @@ struct lbm_ctx {
 
 namespace {
 
-void set_geometry(lbm_ctx* c, int tile_x, int tile_y) {
-  Geometry& g = c->g;
-  g.nx = c->p.nx;
-  g.ny = c->p.ny;
-  g.pitch = pitch_of(c->p);
+// Tiles of a launch: strips of `width` stored columns (tile_x for one step per
+// pass, tile_x - 6 for two) and row blocks of tile_y rows.
+Geometry make_geometry(const lbm_params& p, int tile_x, int tile_y, int width) {
+  Geometry g{};
+  g.nx = p.nx;
+  g.ny = p.ny;
+  g.pitch = pitch_of(p);
   g.plane = (long long)g.ny * g.pitch;
   g.tile_x = tile_x;
   g.tile_y = tile_y;
-  g.nstrips = (g.nx + tile_x - 1) / tile_x;
+  g.nstrips = (g.nx + width - 1) / width;
   g.nrowblocks = (g.ny + tile_y - 1) / tile_y;
   g.nblocks = g.nstrips * g.nrowblocks;
+  return g;
+}
+
+void set_geometry(lbm_ctx* c, int tile_x, int tile_y) {
+  c->g = make_geometry(c->p, tile_x, tile_y, tile_x);
+}
+
+void set_geometry2(lbm_ctx* c, int tile_x, int tile_y) {
+  c->g2 = make_geometry(c->p, tile_x, tile_y, tile_x - kStep2Halo);
 }
 
 // Default launch shape: strips as wide as the lattice allows (up to 256
@@ -367,6 +380,8 @@ lbm_status make_ctx(const lbm_params* p, void* stream, void* ba, void* bb, size_
   int tx, ty;
   default_launch(*p, &tx, &ty);
   set_geometry(c, tx, ty);
+  set_geometry2(c, p->nx >= 256 ? 256 : 128, std::min(64, p->ny));
+  c->fuse = 1;
   c->buf_bytes = 9 * (size_t)c->g.plane * elem_size(*p);
   c->step = 0;
   c->cur = 0;
@@ -529,22 +544,40 @@ void lbm_destroy(lbm_ctx* c) {
 
 lbm_status lbm_set_launch(lbm_ctx* c, const lbm_launch* l) {
   if (!c || !l) return fail(LBM_EINVAL, "NULL argument");
+  const int fuse = l->steps_per_pass == 0 ? 1 : l->steps_per_pass;
+  if (fuse != 1 && fuse != 2) return fail(LBM_EINVAL, "steps_per_pass %d not in {1, 2}", l->steps_per_pass);
   int tx = l->tile_x, ty = l->tile_y;
   int dtx, dty;
   default_launch(c->p, &dtx, &dty);
-  if (tx == 0) tx = dtx;
-  if (ty == 0) ty = dty;
-  if (tx != 64 && tx != 128 && tx != 256) return fail(LBM_EINVAL, "tile_x %d not in {64,128,256}", tx);
+  if (fuse == 1) {
+    if (tx == 0) tx = dtx;
+    if (ty == 0) ty = dty;
+    if (tx != 64 && tx != 128 && tx != 256) return fail(LBM_EINVAL, "tile_x %d not in {64,128,256}", tx);
+  } else {
+    if (tx == 0) tx = c->p.nx >= 256 ? 256 : 128;
+    if (ty == 0) ty = 64;
+    if (tx != 128 && tx != 256)
+      return fail(LBM_EINVAL, "tile_x %d not in {128,256} for two steps per pass", tx);
+  }
   if (ty < 1) return fail(LBM_EINVAL, "tile_y %d < 1", ty);
   ty = std::min(ty, c->p.ny);
-  set_geometry(c, tx, ty);
+  if (fuse == 1) {
+    set_geometry(c, tx, ty);
+  } else {
+    // the single step that ends an odd count keeps the default shape
+    set_geometry(c, dtx, dty);
+    set_geometry2(c, tx, ty);
+  }
+  c->fuse = fuse;
   return LBM_OK;
 }
 
 lbm_status lbm_get_launch(const lbm_ctx* c, lbm_launch* l) {
   if (!c || !l) return fail(LBM_EINVAL, "NULL argument");
-  l->tile_x = c->g.tile_x;
-  l->tile_y = c->g.tile_y;
+  const Geometry& g = c->fuse == 2 ? c->g2 : c->g;
+  l->tile_x = g.tile_x;
+  l->tile_y = g.tile_y;
+  l->steps_per_pass = c->fuse;
   return LBM_OK;
 }
 
@@ -591,7 +624,16 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
   if (!c) return fail(LBM_EINVAL, "NULL context");
   if (n < 0) return fail(LBM_EINVAL, "negative step count");
   if (!c->initialized) return fail(LBM_ESTATE, "lbm_step before lbm_init_field");
-  for (int64_t i = 0; i < n; ++i) {
+  int64_t left = n;
+  // two steps per launch: the buffer written holds the state after both
+  if (c->fuse == 2) {
+    for (; left >= 2; left -= 2) {
+      HIP_TRY(launch_step2((lbm_precision)c->p.precision, c->g2, c->m, c->buf[c->cur],
+                           c->buf[1 - c->cur], c->stream));
+      c->cur = 1 - c->cur;
+    }
+  }
+  for (; left > 0; --left) {
     HIP_TRY(launch_step((lbm_precision)c->p.precision, c->g, c->m, c->buf[c->cur],
                         c->buf[1 - c->cur], c->stream));
     c->cur = 1 - c->cur;

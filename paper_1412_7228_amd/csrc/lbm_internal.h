@@ -37,6 +37,11 @@ hipError_t launch_step(lbm_precision prec, const Geometry& g, const ModelConsts&
                        void* fb, hipStream_t s);
 
 // Workgroups of the step kernel (for g.tile_x) that one CU holds at once.
+// Two fused steps per launch (lbm_step.hip): g.tile_x in {128, 256}, strips of
+// g.tile_x - 6 stored columns (g.nstrips counts them).
+hipError_t launch_step2(lbm_precision prec, const Geometry& g, const ModelConsts& m, const void* fa,
+                        void* fb, hipStream_t s);
+constexpr int kStep2Halo = 6;
 hipError_t step_occupancy(lbm_precision prec, const Geometry& g, int eos, int* per_cu);
 
 // f = equilibrium(rho, u) from device FP64 arrays [ny][nx] (ux/uy may be null).

@@ -1,5 +1,7 @@
-// Single-lattice time step: one launch of k_step per step.
+// Single-lattice time step: one launch of k_step per step, or one launch of
+// k_step2 per two steps.
 #include "lbm_tile.h"
+#include "lbm_tile2.h"
 
 namespace lbm {
 
@@ -57,6 +59,65 @@ static hipError_t launch_step_p(const Geometry& g, const ModelConsts& m, const v
     case LBM_EOS_PR: return launch_step_t<T, LBM_EOS_PR>(g, c, fa, fb, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+// Two fused steps over the whole lattice; the same workgroup-to-tile order.
+template <typename T, int EOS, int BX, bool BIG>
+__global__ void __launch_bounds__(BX) k_step2(const T* __restrict__ fa, T* __restrict__ fb,
+                                               const Geometry geo, const DevC<T> c) {
+  __shared__ Tile2Lds<T, BX> lds;
+  static_assert(tile2_width<BX>() == BX - kStep2Halo, "strip width");
+  const int lb = xcd_remap(blockIdx.x, geo.nblocks);
+  const int rb = lb / geo.nstrips;
+  const int strip = lb - rb * geo.nstrips;
+  step2_tile<T, EOS, BX, BIG>(fa, fb, geo, c, strip * tile2_width<BX>(), rb * geo.tile_y,
+                              (rb & 1) != 0, lds);
+}
+
+template <typename T, int EOS, bool BIG>
+static hipError_t launch_step2_b(const Geometry& g, const DevC<T>& c, const void* fa, void* fb,
+                                 hipStream_t s) {
+  const T* a = static_cast<const T*>(fa);
+  T* b = static_cast<T*>(fb);
+  switch (g.tile_x) {
+    case 128:
+      hipLaunchKernelGGL((k_step2<T, EOS, 128, BIG>), dim3(g.nblocks), dim3(128), 0, s, a, b, g, c);
+      break;
+    case 256:
+      hipLaunchKernelGGL((k_step2<T, EOS, 256, BIG>), dim3(g.nblocks), dim3(256), 0, s, a, b, g, c);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T, int EOS>
+static hipError_t launch_step2_t(const Geometry& g, const DevC<T>& c, const void* fa, void* fb,
+                                 hipStream_t s) {
+  const unsigned long long bytes = 9ull * (unsigned long long)g.plane * sizeof(T);
+  if (bytes < (1ull << 32)) return launch_step2_b<T, EOS, false>(g, c, fa, fb, s);
+  if ((unsigned long long)g.plane * sizeof(T) >= (1ull << 32)) return hipErrorInvalidValue;
+  return launch_step2_b<T, EOS, true>(g, c, fa, fb, s);
+}
+
+template <typename T>
+static hipError_t launch_step2_p(const Geometry& g, const ModelConsts& m, const void* fa, void* fb,
+                                 hipStream_t s) {
+  const DevC<T> c = make_devc<T>(m);
+  switch (m.eos) {
+    case LBM_EOS_IDEAL: return launch_step2_t<T, LBM_EOS_IDEAL>(g, c, fa, fb, s);
+    case LBM_EOS_CS: return launch_step2_t<T, LBM_EOS_CS>(g, c, fa, fb, s);
+    case LBM_EOS_VDW: return launch_step2_t<T, LBM_EOS_VDW>(g, c, fa, fb, s);
+    case LBM_EOS_PR: return launch_step2_t<T, LBM_EOS_PR>(g, c, fa, fb, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_step2(lbm_precision prec, const Geometry& g, const ModelConsts& m, const void* fa,
+                        void* fb, hipStream_t s) {
+  if (prec == LBM_FP32) return launch_step2_p<float>(g, m, fa, fb, s);
+  return launch_step2_p<double>(g, m, fa, fb, s);
 }
 
 template <typename T, int EOS>

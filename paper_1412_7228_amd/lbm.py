@@ -65,7 +65,8 @@ class Obs(ctypes.Structure):
 
 
 class Launch(ctypes.Structure):
-    _fields_ = [("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32)]
+    _fields_ = [("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32),
+                ("steps_per_pass", ctypes.c_int32)]
 
 
 class BatchLaunch(ctypes.Structure):
@@ -90,6 +91,11 @@ def load_library(path: str | None = None):
     path = path or LIB_PATH
     if not os.path.exists(path):
         raise FileNotFoundError(f"{path} is not built (python -m paper_1412_7228_amd.build)")
+    # torch first: the library must bind to the HIP runtime that torch loads (its
+    # buffers and streams are torch's); loaded first, the library would pull in a
+    # second HIP/HSA runtime that cannot open the device
+    import torch  # noqa: F401
+
     lib = ctypes.CDLL(path)
     vp, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)
     fp = ctypes.POINTER(ctypes.c_float)
@@ -230,13 +236,14 @@ class Lattice:
 
     # -- launch shape --------------------------------------------------------
     @property
-    def launch(self) -> tuple[int, int]:
+    def launch(self) -> tuple[int, int, int]:
+        """(tile_x, tile_y, steps_per_pass) of the step launches."""
         l = Launch()
         _check(self.lib.lbm_get_launch(self.h, ctypes.byref(l)))
-        return l.tile_x, l.tile_y
+        return l.tile_x, l.tile_y, l.steps_per_pass
 
-    def set_launch(self, tile_x: int = 0, tile_y: int = 0):
-        l = Launch(int(tile_x), int(tile_y))
+    def set_launch(self, tile_x: int = 0, tile_y: int = 0, steps_per_pass: int = 0):
+        l = Launch(int(tile_x), int(tile_y), int(steps_per_pass))
         _check(self.lib.lbm_set_launch(self.h, ctypes.byref(l)))
 
     # -- state ---------------------------------------------------------------

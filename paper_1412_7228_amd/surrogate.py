@@ -5,7 +5,9 @@ A small network (the library's ``lbm_mlp_*`` kernels) maps
 the batched engine.  To reach a target surface tension sigma* at a given
 (A, T/Tc), the network is inverted for kappa and the prediction is checked
 by one real lattice run; if that run misses by more than 2 %, the plain
-kappa sweep is the fallback.  Two baselines without the network are counted
+kappa sweep is the fallback.  Two networks are trained on the same runs: one
+on log sigma itself, one on log sigma - log(1 - kappa) (Eq. 28 as a prior);
+both keep the weights with the lowest loss on a held-out fifth of the runs.  Two baselines without the network are counted
 the same way: the plain sweep (kappa on a 0.1 grid over [0, 0.8], bracket,
 interpolate, verify) and the secant guided by Eq. (28)'s sigma proportional
 to (1 - kappa) (a kappa = 0 run, then kappa = 1 - sigma*/sigma_0, verify,
@@ -55,30 +57,61 @@ def init_params(seed: int, nparams: int = 33923) -> np.ndarray:
 
 class Surrogate:
     """(A, kappa, T/Tc) -> (sigma, rho_l, rho_v) through the library's network kernels.
-    Targets are learned as (log sigma, rho_l, log rho_v), standardised."""
+    Targets are learned as (log sigma, rho_l, log rho_v), standardised.  With
+    ``prior_eq28`` the network learns log sigma - log(1 - kappa) instead, i.e. only
+    the departure from Eq. (28)'s sigma proportional to (1 - kappa)."""
 
-    def __init__(self, seed: int = 0, max_batch: int = 1024):
+    def __init__(self, seed: int = 0, max_batch: int = 1024, prior_eq28: bool = False):
         self.net = lbm.MLP(max_batch=max_batch)
         self.net.set_params(init_params(seed, self.net.nparams))
         self.mu = np.zeros(3)
         self.sd = np.ones(3)
+        self.prior = bool(prior_eq28)
 
-    @staticmethod
-    def _targets(Y):
-        Y = np.asarray(Y, float)
-        return np.stack([np.log(Y[:, 0]), Y[:, 1], np.log(Y[:, 2])], axis=1)
+    def _targets(self, X, Y):
+        X, Y = np.asarray(X, float), np.asarray(Y, float)
+        ls = np.log(Y[:, 0]) - (np.log1p(-X[:, 1]) if self.prior else 0.0)
+        return np.stack([ls, Y[:, 1], np.log(Y[:, 2])], axis=1)
 
-    def fit(self, X, Y, iters: int = 4000, lr: float = 2e-3) -> np.ndarray:
-        """X: [n, 3] (A, kappa, T/Tc); Y: [n, 3] (sigma, rho_l, rho_v).  Full-batch Adam."""
-        t = self._targets(Y)
-        self.mu, self.sd = t.mean(0), t.std(0) + 1e-12
+    def fit(self, X, Y, iters: int = 3000, lr: float = 1e-3, val_frac: float = 0.2,
+            check_every: int = 25, seed: int = 0) -> dict:
+        """X: [n, 3] (A, kappa, T/Tc); Y: [n, 3] (sigma, rho_l, rho_v).  Full-batch Adam on
+        a random (1 - val_frac) of the samples; the weights kept are those with the
+        lowest sigma error on the held-out rest (checked every `check_every` steps),
+        since ~400 noisy samples cannot pin 33,923 parameters.  Returns the loss
+        histories."""
         X = np.asarray(X, float)
-        self.net.set_data(features(X[:, 0], X[:, 1], X[:, 2]), ((t - self.mu) / self.sd).astype(np.float32))
-        return self.net.train(iters, lr)
+        t = self._targets(X, Y)
+        g = np.random.Generator(np.random.PCG64(seed + 17))
+        order = g.permutation(len(X))
+        nv = int(round(val_frac * len(X))) if len(X) >= 10 else 0
+        val, tr = order[:nv], order[nv:]
+        self.mu, self.sd = t[tr].mean(0), t[tr].std(0) + 1e-12
+        z = ((t - self.mu) / self.sd).astype(np.float32)
+        feats = features(X[:, 0], X[:, 1], X[:, 2])
+        self.net.set_data(feats[tr], z[tr])
+        train_loss, val_loss = [], []
+        best = (np.inf, self.net.params(), 0)
+        done = 0
+        while done < iters:
+            k = min(check_every, iters - done)
+            train_loss.extend(float(v) for v in self.net.train(k, lr))
+            done += k
+            if nv:
+                # the inversion uses only sigma: select on its held-out error
+                vl = float(np.mean((self.net.forward(feats[val]).astype(float)[:, 0] - z[val, 0]) ** 2))
+                val_loss.append(vl)
+                if vl < best[0]:
+                    best = (vl, self.net.params(), done)
+        if nv:
+            self.net.set_params(best[1])
+        return dict(train=np.array(train_loss), val=np.array(val_loss), best_iter=best[2],
+                    best_val=float(best[0]) if nv else None)
 
     def predict(self, A, kappa, T) -> np.ndarray:
         y = self.net.forward(features(A, kappa, T)).astype(float) * self.sd + self.mu
-        return np.stack([np.exp(y[:, 0]), y[:, 1], np.exp(y[:, 2])], axis=1)
+        ls = y[:, 0] + (np.log1p(-np.asarray(kappa, float)) if self.prior else 0.0)
+        return np.stack([np.exp(ls), y[:, 1], np.exp(y[:, 2])], axis=1)
 
     def invert_kappa(self, A, T, sigma_target, grid: int = 801) -> np.ndarray:
         """kappa in KAPPA_RANGE whose predicted sigma equals each target (linear
@@ -131,14 +164,22 @@ def verify(specs, steps: int, n: int = 200, R: float = 40.0):
     return np.array([r["sigma"] if r["ok"] else np.nan for r in res])
 
 
-def study(seed: int = 0, n_targets: int = 64, train_batches: int = 2, train_steps: int = 20000,
-          verify_steps: int = 20000, side=(64, 512), domains: int = 256, iters: int = 4000,
-          log=print) -> dict:
+def _num(x):
+    return float(x) if np.isfinite(x) else None
+
+
+def study(seed: int = 0, n_targets: int = 64, train_batches: int = 2, train_steps: int = 60000,
+          verify_steps: int = 20000, side=(64, 512), domains: int = 256, iters: int = 3000,
+          lr: float = 1e-3, log=print) -> dict:
     t_start = time.time()
     X, Y, bad = training_set(train_batches, seed, train_steps, side=side, domains=domains, log=log)
-    sur = Surrogate(seed=seed)
-    loss = sur.fit(X, Y, iters=iters)
-    log(f"[surrogate] trained on {len(X)} runs: loss {loss[0]:.3e} -> {loss[-1]:.3e}")
+    surs, hists = {}, {}
+    for name, prior in (("plain", False), ("eq28_prior", True)):
+        surs[name] = Surrogate(seed=seed, prior_eq28=prior)
+        hists[name] = surs[name].fit(X, Y, iters=iters, lr=lr, seed=seed)
+        h = hists[name]
+        log(f"[surrogate] {name}: trained on {len(X)} runs: loss {h['train'][0]:.3e} -> "
+            f"{h['train'][-1]:.3e}, held-out best {h['best_val']} at step {h['best_iter']}")
     # targets: (A, T/Tc) from the training distribution; sigma* = s sigma_0, s log-uniform in [0.2, 1]
     g = inputs.rng(seed + 1000)
     A = g.uniform(-0.7, -0.3, n_targets)
@@ -192,30 +233,47 @@ def study(seed: int = 0, n_targets: int = 64, train_batches: int = 2, train_step
     sec_runs[~sec_ok] += sweep_runs[~sec_ok]  # fall back to the sweep
 
     # surrogate: invert, verify once; fall back to the sweep if the check misses
-    k_sur = np.zeros(n_targets)  # targets without a two-phase kappa = 0 run are not counted
-    k_sur[valid] = sur.invert_kappa(A[valid], T[valid], target[valid])
-    sig_sur = verify([(a, k, t) for a, k, t in zip(A, k_sur, T)], verify_steps)
-    sur_ok = hit(sig_sur, target)
-    sur_runs = np.where(sur_ok, 1.0, 1.0 + sweep_runs)
-    sur_final_ok = sur_ok | sweep_ok
-
     def stats(runs, ok):
         m = valid
         return dict(mean_runs=float(runs[m].mean()), success=float(ok[m].mean()),
                     first_try_success=None)
 
+    sur_rep, diag = {}, {}
+    for name, sur in surs.items():
+        k_sur = np.zeros(n_targets)  # targets without a two-phase kappa = 0 run are not counted
+        k_sur[valid] = sur.invert_kappa(A[valid], T[valid], target[valid])
+        sig_sur = verify([(a, k, t) for a, k, t in zip(A, k_sur, T)], verify_steps)
+        sur_ok = hit(sig_sur, target)
+        sur_runs = np.where(sur_ok, 1.0, 1.0 + sweep_runs)
+        pred0 = sur.predict(A, np.zeros(n_targets), T)[:, 0]
+        pred_sur = sur.predict(A, k_sur, T)[:, 0]
+        train_pred = sur.predict(X[:, 0], X[:, 1], X[:, 2])[:, 0]
+        h = hists[name]
+        sur_rep[name] = dict(stats(sur_runs, sur_ok | sweep_ok), first_try_success=float(sur_ok[valid].mean()),
+                             median_abs_error=float(np.nanmedian(np.abs(sig_sur[valid] / target[valid] - 1))),
+                             heldout_best=h["best_val"], heldout_best_iter=int(h["best_iter"]),
+                             loss_first=float(h["train"][0]), loss_last=float(h["train"][-1]))
+        diag[name] = dict(
+            train_median_rel_error=float(np.median(np.abs(train_pred / Y[:, 0] - 1))),
+            kappa0_median_rel_error=float(np.nanmedian(np.abs(pred0[valid] / sigma0[valid] - 1))),
+            targets=[dict(A=float(A[i]), T_over_Tc=float(T[i]), sigma0=_num(sigma0[i]),
+                          sigma0_pred=float(pred0[i]), target=_num(target[i]), kappa_sur=float(k_sur[i]),
+                          sigma_sur=_num(sig_sur[i]), sigma_sur_pred=float(pred_sur[i]),
+                          kappa_sweep=_num(k_sweep[i]), sigma_sweep=_num(sig_sweep[i]))
+                     for i in range(n_targets)])
+
     rep = dict(
         config=dict(seed=seed, n_targets=n_targets, train_batches=train_batches, domains=domains,
                     train_steps=train_steps, verify_steps=verify_steps, side=list(side),
-                    verify_lattice=200, verify_radius=40, tolerance=TOLERANCE),
-        training=dict(samples=int(len(X)), outside_model_range=int(bad),
-                      loss_first=float(loss[0]), loss_last=float(loss[-1])),
+                    verify_lattice=200, verify_radius=40, tolerance=TOLERANCE, iters=iters, lr=lr),
+        training=dict(samples=int(len(X)), outside_model_range=int(bad)),
         targets_valid=int(valid.sum()),
-        surrogate=dict(stats(sur_runs, sur_final_ok), first_try_success=float(sur_ok[valid].mean()),
-                       median_abs_error=float(np.nanmedian(np.abs(sig_sur[valid] / target[valid] - 1)))),
+        surrogate=sur_rep["plain"],
+        surrogate_eq28_prior=sur_rep["eq28_prior"],
         plain_sweep=dict(stats(sweep_runs, sweep_ok),
                          median_abs_error=float(np.nanmedian(np.abs(sig_sweep[valid] / target[valid] - 1)))),
         secant_eq28=dict(stats(sec_runs, sec_ok | sweep_ok)),
+        diagnostics=diag,
         seconds=time.time() - t_start,
     )
     return rep
@@ -227,12 +285,14 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--targets", type=int, default=64)
     ap.add_argument("--train-batches", type=int, default=2)
-    ap.add_argument("--train-steps", type=int, default=20000)
+    ap.add_argument("--train-steps", type=int, default=60000,
+                    help="steps of the training droplets (large drops relax slowly)")
     ap.add_argument("--verify-steps", type=int, default=20000)
-    ap.add_argument("--iters", type=int, default=4000)
+    ap.add_argument("--iters", type=int, default=3000)
+    ap.add_argument("--lr", type=float, default=1e-3)
     a = ap.parse_args()
     rep = study(seed=a.seed, n_targets=a.targets, train_batches=a.train_batches,
-                train_steps=a.train_steps, verify_steps=a.verify_steps, iters=a.iters,
+                train_steps=a.train_steps, verify_steps=a.verify_steps, iters=a.iters, lr=a.lr,
                 log=lambda m: print(m, flush=True))
     with open(a.out, "w") as f:
         json.dump(rep, f, indent=1)

@@ -274,3 +274,72 @@ def test_density_dependent_viscosity(lbm, oracle_mod, precision):
         if k in ("ux", "uy") and precision == "fp32":
             continue
         assert rel_field(k, gg[k], og[k]) < tol, (k, rel_field(k, gg[k], og[k]))
+
+
+# ---------------------------------------------------------------------------
+# Two steps per launch (temporal blocking): bitwise the same states as single
+# steps, for ragged strips and row blocks, lattices narrower than a strip,
+# odd step counts (the last step runs alone) and every EOS.
+# ---------------------------------------------------------------------------
+TWO_STEP_CASES = [
+    # (nx, ny, eos cfg, tile_x, tile_y, steps)
+    (300, 200, dict(eos="cs", T_over_Tc=0.7, A=-0.5, kappa=0.3), 256, 64, 20),
+    (37, 23, dict(eos="cs", T_over_Tc=0.8, A=-0.6, kappa=0.0), 128, 8, 7),
+    (250, 64, dict(eos="vdw", K=0.3, T_over_Tc=0.9, A=0.5, kappa=0.9), 256, 13, 9),
+    (1000, 130, dict(eos="pr", K=0.5, T_over_Tc=0.8, A=-0.3, kappa=0.5), 128, 32, 12),
+    (122, 122, dict(eos="ideal", A=-0.5, kappa=0.2), 128, 64, 6),
+    (501, 77, dict(eos="cs", T_over_Tc=0.75, A=-0.4, kappa=0.6, nu_gas=0.2, nu_liquid=0.1), 256, 16, 11),
+]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("case", range(len(TWO_STEP_CASES)))
+def test_two_steps_per_pass_bitwise_equal_single_steps(lbm, precision, case):
+    nx, ny, phys, tx, ty, steps = TWO_STEP_CASES[case]
+    say(f"two-step pass {nx}x{ny} {phys['eos']} {precision} tile {tx}x{ty} steps {steps}")
+    cfg = dict(phys, nx=nx, ny=ny, precision=precision)
+    if cfg["eos"] == "ideal":
+        rho0 = 1.0 + 0.05 * inputs.rng(case).uniform(-1, 1, (ny, nx))
+    else:
+        rv, rl = lbm.coexistence({k: v for k, v in cfg.items() if k not in ("nu_gas", "nu_liquid")})
+        if "nu_gas" in cfg:
+            cfg.update(rho_gas=rv, rho_liquid=rl)
+        rho0 = inputs.droplet(nx, ny, 0.3 * min(nx, ny), rl, rv, W=4.0, noise=1e-2, seed=case)
+    one = lbm.Lattice(cfg)
+    one.set_launch(0, 0, 1)
+    two = lbm.Lattice(cfg)
+    two.set_launch(tx, ty, 2)
+    assert two.launch == (tx, min(ty, ny), 2)
+    for lat in (one, two):
+        lat.init_field(rho0)
+        lat.step(steps)
+    assert np.array_equal(two.f_soa(), one.f_soa())
+    # and in pieces: an odd split, then the rest
+    two.step(3)
+    two.step(4)
+    one.step(7)
+    assert np.array_equal(two.f_soa(), one.f_soa())
+
+
+def test_two_steps_per_pass_matches_oracle_fp64(lbm, oracle_mod):
+    say("two-step pass vs oracle, 100x100 droplet, 200 steps")
+    cfg = dict(nx=100, ny=100, eos="cs", T_over_Tc=0.8, A=-0.5, kappa=0.0, precision="fp64")
+    rv, rl = cs_maxwell(0.8)
+    rho0 = inputs.droplet(100, 100, 25, rl, rv, W=5.0, noise=1e-3, seed=0)
+    lat = lbm.Lattice(cfg)
+    lat.set_launch(128, 16, 2)
+    lat.init_field(rho0)
+    lat.step(200)
+    o = oracle_mod.Oracle(cfg, nthreads=8)
+    o.init_field(rho0)
+    o.run(200)
+    ref = o.f_soa()
+    assert rel(lat.f_soa(), ref) < 1e-12
+
+
+def test_two_steps_per_pass_rejects_narrow_tile(lbm):
+    lat = lbm.Lattice(dict(nx=64, ny=64, eos="cs", precision="fp32"))
+    with pytest.raises(lbm.LBMError):
+        lat.set_launch(64, 16, 2)
+    with pytest.raises(lbm.LBMError):
+        lat.set_launch(128, 16, 3)
