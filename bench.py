@@ -4,15 +4,20 @@
 Workload: a single 4096 x 4096 periodic lattice, spinodal decomposition from
 the mean of the Carnahan-Starling coexistence densities at 0.7Tc
 (rho = 0.183713 (1 + 0.01 xi), xi ~ U[-1, 1), seed 0), A = -0.5, kappa = 0,
-FP32 distributions; the FP64 variant is measured beside it.  A step is one
-launch of the fused kernel (density/psi pass, force, pressure-tensor term,
-MRT collision, streaming) over the whole lattice.
+FP32 distributions; the FP64 variant is measured beside it.  A lattice update
+is the density/psi pass, force, pressure-tensor term, MRT collision and
+streaming of one cell; the library's default launch fuses two time steps per
+kernel launch (each launch reads and writes the state once).
 
-Prints ONE JSON line:  value = MLUPS (million lattice updates per second),
-roofline = algorithmic HBM bytes (9 loads + 9 stores per update: 72 B in
-FP32, 144 B in FP64) per launch / measured launch time, against 8 TB/s, and
-cpu_baseline = the FP64 CPU oracle on the host cores on a bounded sample of
-the same lattice.
+Prints ONE JSON line:  value = MLUPS (million lattice updates per second).
+roofline = the bound of the dominant kernel: with two steps per launch the
+kernel is bound by vector ALU issue, so achieved = algorithmic FP operations
+(FLOPS_PER_LU per update, counted in the single-step kernel's gfx950 ISA, FMA
+= 2) per launch / measured launch time, against the FP32 (or FP64) vector
+peak without packed math; with one step per launch it is HBM-bound, and
+achieved = 72 B (FP32) / 144 B (FP64) per update / launch time, against
+8 TB/s.  cpu_baseline = the FP64 CPU oracle on the host cores on a bounded
+sample of the same lattice.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -30,6 +35,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+# vector ALU peak without packed math: 256 CUs x 64 lanes x 2 (FMA) x 2.4 GHz;
+# the same for FP32 and FP64 on MI355X (packed FP32 is not used by this build)
+ALU_PEAK_TFLOPS = {"fp32": 78.6, "fp64": 78.6}
+FLOPS_PER_LU = 260  # FP arithmetic of one cell update in the single-step kernel's ISA
 N = 4096
 RHO_MEAN = 0.183713  # (rho_v + rho_l)/2 of CS at 0.7Tc: (0.00929415 + 0.35813094)/2
 WORKLOAD = dict(nx=N, ny=N, eos="cs", T_over_Tc=0.7, A=-0.5, kappa=0.0)
@@ -96,13 +105,27 @@ def gpu_measure(precision, steps, warmup, tile):
     if tile:
         lat.set_launch(*tile)
     lat.init_field(inputs.spinodal(N, N, RHO_MEAN, noise=1e-2, seed=0))
+    spp = lat.launch[2]
+    if steps % spp:
+        steps += spp - steps % spp  # whole launches only
     ms = time_steps(lat, steps, warmup)
     ob = lat.observables(check=False)
     lus = float(N * N) * steps
-    per_launch_s = ms * 1e-3 / steps
-    achieved = BYTES_PER_LU[precision] * N * N / per_launch_s / 1e9
-    res = dict(ms_per_step=ms / steps, mlups=lus / (ms * 1e-3) / 1e6, achieved_gbs=achieved,
-               tile=list(lat.launch), mass=ob["mass"], n_nonfinite=ob["n_nonfinite"])
+    launches = steps // spp
+    per_launch_s = ms * 1e-3 / launches
+    # bytes the launch must move: the state in and out once per launch
+    gbs = BYTES_PER_LU[precision] * N * N / per_launch_s / 1e9
+    tflops = FLOPS_PER_LU * N * N * spp / per_launch_s / 1e12
+    if spp == 2:
+        roof = dict(bound="alu", achieved=round(tflops, 2), peak=ALU_PEAK_TFLOPS[precision],
+                    unit="TFLOP/s", frac=round(tflops / ALU_PEAK_TFLOPS[precision], 4), traffic=None,
+                    hbm_gbs=round(gbs, 1))
+    else:
+        roof = dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(gbs / HBM_PEAK_GBS, 4), traffic=None)
+    res = dict(ms_per_step=ms / steps, mlups=lus / (ms * 1e-3) / 1e6, steps=steps,
+               launch_ms=per_launch_s * 1e3, roofline=roof, tile=list(lat.launch), mass=ob["mass"],
+               n_nonfinite=ob["n_nonfinite"])
     lat.close()
     return res
 
@@ -139,7 +162,7 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(1)
-    tile = tuple(int(v) for v in a.tile.split(",")) if a.tile else None
+    tile = tuple(int(v) for v in a.tile.split(",")) if a.tile else None  # tx,ty[,steps_per_pass]
     print(f"[bench] fp32 {N}x{N}: warmup {a.warmup}, timed {a.steps}", file=sys.stderr, flush=True)
     r32 = gpu_measure("fp32", a.steps, a.warmup, tile)
     print(f"[bench] fp32 {r32}", file=sys.stderr, flush=True)
@@ -161,7 +184,7 @@ def main():
         "value": round(r32["mlups"], 1),
         "unit": "MLUPS",
         "n_gpus": 1,
-        "steps": a.steps,
+        "steps": r32["steps"],
         "warmup": a.warmup,
         "ms_per_step": r32["ms_per_step"],
         "higher_is_better": True,
@@ -173,22 +196,15 @@ def main():
             "workload": "single 4096x4096 periodic lattice, spinodal decomposition, CS EOS, T/Tc=0.7, "
                         "A=-0.5, kappa=0, FP32 distributions",
             "lattice": [N, N],
-            "launch_tile": r32["tile"],
+            "launch": {"tile": r32["tile"][:2], "steps_per_pass": r32["tile"][2],
+                       "launch_ms": r32["launch_ms"]},
         },
-        "roofline": {
-            "bound": "hbm",
-            "achieved": round(r32["achieved_gbs"], 1),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(r32["achieved_gbs"] / HBM_PEAK_GBS, 4),
-            "traffic": None,
-        },
+        "roofline": r32["roofline"],
         "fp64_variant": None if r64 is None else {
-            "value": round(r64["mlups"], 1), "unit": "MLUPS", "steps": a.fp64_steps,
-            "ms_per_step": r64["ms_per_step"],
-            "roofline": {"bound": "hbm", "achieved": round(r64["achieved_gbs"], 1),
-                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": round(r64["achieved_gbs"] / HBM_PEAK_GBS, 4)},
+            "value": round(r64["mlups"], 1), "unit": "MLUPS", "steps": r64["steps"],
+            "ms_per_step": r64["ms_per_step"], "launch": {"tile": r64["tile"][:2],
+                                                          "steps_per_pass": r64["tile"][2]},
+            "roofline": r64["roofline"],
         },
         "cpu_baseline": cpu,
         "copy_ceiling": None if copy is None else {

@@ -119,7 +119,9 @@ typedef struct {
  *     the state once; bitwise the same states as single steps); tile_x in
  *     {128, 256}, of which tile_x - 6 columns are stored per strip.  An odd
  *     step count ends with one single-step launch of the default shape.
- * tile_y >= 1.  0 in any field selects the library default for the lattice. */
+ * tile_y >= 1.  0 in a tile field selects the library default for the
+ * lattice; steps_per_pass 0 selects 2, or 1 with tile_x = 64.  New contexts
+ * start with two steps per pass and the default two-step shape. */
 typedef struct {
   int32_t tile_x, tile_y;
   int32_t steps_per_pass;
@@ -225,6 +227,10 @@ typedef struct {
   int32_t grid;             /* workgroups per launch                                  */
   int32_t ntiles;           /* tiles over all domains                                 */
   int32_t resident_per_cu;  /* persistent mode: workgroups one CU holds at once       */
+  /* input again: */
+  int32_t steps_per_pass;   /* per-step mode: 1, or 2 = two fused steps per launch as in
+                               lbm_launch (tile_x in {128, 256}; an odd count ends with
+                               one single-step launch); 0 = 1                          */
 } lbm_batch_launch;
 
 /* Creates a batch of n domains with parameters params[0..n).  Allocates one

@@ -11,12 +11,15 @@ from __future__ import annotations
 import json
 import os
 
-LATTICE_CANDIDATES = [(256, 8), (256, 16), (256, 32), (256, 64), (256, 128), (128, 16), (128, 32),
-                      (128, 64), (64, 32), (64, 64)]
-# (the persistent mode is switched off in the library for now)
-BATCH_CANDIDATES = [("per_step", 64, 8), ("per_step", 64, 16), ("per_step", 64, 32),
-                    ("per_step", 64, 64), ("per_step", 128, 16), ("per_step", 128, 32),
-                    ("per_step", 128, 64)]
+# (tile_x, tile_y, steps_per_pass)
+LATTICE_CANDIDATES = [(256, 16, 1), (256, 64, 1), (128, 32, 1), (64, 32, 1),
+                      (256, 12, 2), (256, 16, 2), (256, 20, 2), (256, 24, 2), (256, 32, 2),
+                      (128, 16, 2), (128, 32, 2), (128, 64, 2)]
+# (mode, tile_x, tile_y, steps_per_pass); the persistent mode is switched off in
+# the library for now
+BATCH_CANDIDATES = [("per_step", 64, 16, 1), ("per_step", 64, 32, 1), ("per_step", 128, 16, 1),
+                    ("per_step", 128, 8, 2), ("per_step", 128, 16, 2), ("per_step", 128, 32, 2),
+                    ("per_step", 256, 8, 2), ("per_step", 256, 16, 2), ("per_step", 256, 32, 2)]
 
 
 def cache_path() -> str:
@@ -62,21 +65,22 @@ def _time(stream, fn, steps: int) -> float:
 
 
 def tune_lattice(lat, steps: int = 40, candidates=None, use_cache: bool = True) -> dict:
-    """Pick the fastest (tile_x, tile_y) for a Lattice (its state advances by the
-    timing steps).  Returns {"tile": [tx, ty], "ms": ..., "table": [...]}."""
+    """Pick the fastest (tile_x, tile_y, steps_per_pass) for a Lattice (its state
+    advances by the timing steps).  Returns {"tile": [tx, ty, spp], "ms": ...,
+    "table": [...]} with ms per step."""
     c = lat.cfg
     key = f"lattice|{_device()}|{lat.nx}x{lat.ny}|{c['precision']}|{c['eos']}"
     cache = _load() if use_cache else {}
-    if key in cache:
+    if key in cache and len(cache[key]["tile"]) == 3:
         lat.set_launch(*cache[key]["tile"])
         return cache[key]
     table = []
-    for tx, ty in candidates or LATTICE_CANDIDATES:
-        if tx > 64 and lat.nx < tx:
+    for tx, ty, spp in candidates or LATTICE_CANDIDATES:
+        if tx > 64 and lat.nx < tx - (6 if spp == 2 else 0):
             continue
-        lat.set_launch(tx, min(ty, lat.ny))
-        lat.step(5)
-        table.append(((tx, min(ty, lat.ny)), _time(lat.stream, lat.step, steps)))
+        lat.set_launch(tx, min(ty, lat.ny), spp)
+        lat.step(6)
+        table.append(((tx, min(ty, lat.ny), spp), _time(lat.stream, lat.step, steps)))
     best = min(table, key=lambda t: t[1])
     lat.set_launch(*best[0])
     res = {"tile": list(best[0]), "ms": best[1], "table": [[list(t), m] for t, m in table]}
@@ -86,25 +90,28 @@ def tune_lattice(lat, steps: int = 40, candidates=None, use_cache: bool = True) 
 
 
 def tune_batch(batch, steps: int = 20, candidates=None, use_cache: bool = True) -> dict:
-    """Pick the fastest (mode, tile_x, tile_y) for a Batch (its state advances)."""
+    """Pick the fastest (mode, tile_x, tile_y, steps_per_pass) for a Batch (its
+    state advances).  ms is per step."""
     sizes = sorted(f"{ny}x{nx}" for ny, nx in batch.shapes)
     sig = str(abs(hash(",".join(sizes))) % (10 ** 12))
     c = batch.cfgs[0]
     key = f"batch|{_device()}|{len(sizes)}|{sig}|{c['precision']}|{c['eos']}"
     cache = _load() if use_cache else {}
-    if key in cache:
-        batch.set_launch(*cache[key]["launch"])
+    if key in cache and len(cache[key]["launch"]) == 4:
+        mode, tx, ty, spp = cache[key]["launch"]
+        batch.set_launch(mode, tx, ty, steps_per_pass=spp)
         return cache[key]
     table = []
-    for mode, tx, ty in candidates or BATCH_CANDIDATES:
-        batch.set_launch(mode, tx, ty)
+    for mode, tx, ty, spp in candidates or BATCH_CANDIDATES:
+        batch.set_launch(mode, tx, ty, steps_per_pass=spp)
         batch.step(2)
         batch.sync()
         ms = _time(batch.stream, batch.step, steps)
         batch.sync()
-        table.append(((mode, tx, ty), ms))
+        table.append(((mode, tx, ty, spp), ms))
     best = min(table, key=lambda t: t[1])
-    batch.set_launch(*best[0])
+    mode, tx, ty, spp = best[0]
+    batch.set_launch(mode, tx, ty, steps_per_pass=spp)
     res = {"launch": list(best[0]), "ms": best[1], "table": [[list(t), m] for t, m in table]}
     cache[key] = res
     _store(cache)

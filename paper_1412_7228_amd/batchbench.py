@@ -3,9 +3,10 @@
 256 independent Laplace droplets, square domains with side uniform in
 {64..512}, R = u * side with u ~ U[0.15, 0.35], T/Tc ~ U[0.6, 0.85],
 kappa ~ U[0, 0.8], A ~ U[-0.7, -0.3] (seeded), FP32, CS EOS.  Times the
-per-step launch mode (one launch per step, in HIP graphs) for two tile shapes
-with HIP events on the batch's stream and prints one JSON line: MLUPS over
-all domains, the launch shapes, and how many domains stayed two-phase.
+per-step launch mode (launches in HIP graphs) with one step per launch and
+with two fused steps per launch, with HIP events on the batch's stream, and
+prints one JSON line: MLUPS over all domains, the launch shapes, and how many
+domains stayed two-phase.
 
     python -m paper_1412_7228_amd.batchbench [--steps 20000] [--domains 256]
 """
@@ -32,10 +33,10 @@ def build(domains: int, seed: int, precision: str = "fp32"):
     return b, cases, cells
 
 
-def time_mode(b, mode, tile, steps):
+def time_mode(b, mode, tile, steps, steps_per_pass=1):
     import torch
 
-    b.set_launch(mode, *tile)
+    b.set_launch(mode, *tile, steps_per_pass=steps_per_pass)
     b.step(10)
     b.sync()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -62,11 +63,12 @@ def main():
         tuned = autotune.tune_batch(b, steps=20, use_cache=False)
         print(f"[batch] autotune {tuned}", flush=True)
     res = {}
-    for mode, tile in (("per_step", (64, 32)), ("per_step", (64, 16))):
-        ms = time_mode(b, mode, tile, a.steps)
-        key = f"{mode}_{tile[0]}x{tile[1]}"
+    for mode, tile, spp in (("per_step", (64, 16), 1), ("per_step", (128, 16), 2),
+                            ("per_step", (256, 16), 2)):
+        ms = time_mode(b, mode, tile, a.steps, spp)
+        key = f"{mode}{'2' if spp == 2 else ''}_{tile[0]}x{tile[1]}"
         res[key] = dict(ms=ms, mlups=cells * a.steps / (ms * 1e-3) / 1e6, tile=list(tile),
-                        grid=b.launch["grid"], ntiles=b.launch["ntiles"])
+                        steps_per_pass=spp, grid=b.launch["grid"], ntiles=b.launch["ntiles"])
         print(f"[batch] {key} {res[key]}", flush=True)
     obs = b.observables()
     ok = sum(1 for c, o in zip(cases, obs) if o["n_nonfinite"] == 0 and o["rho_in"] > 1.5 * o["rho_out"] > 0)

@@ -357,6 +357,23 @@ void default_launch(const lbm_params& p, int* tx, int* ty) {
   *ty = std::min(rows, p.ny);
 }
 
+// Default shape of the two-step launch: 256-lane strips (250 stored columns)
+// where the lattice is that wide, else 128; 20 rows (FP32) or 32 rows (FP64)
+// per workgroup, fewer while that leaves under 4 workgroups per CU.  (On the
+// 4096^2 lattice 14 to 28 rows are within 1.5% of each other in FP32, 16 to 32
+// in FP64; 8 rows lose 12%, 64 rows 15% from the tail of the grid.)
+void default_launch2(const lbm_params& p, int* tx, int* ty) {
+  *tx = p.nx >= 250 ? 256 : 128;
+  int cus = 0, dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+    cus = 256;
+  const long long strips = (p.nx + *tx - kStep2Halo - 1) / (*tx - kStep2Halo);
+  int rows = p.precision == LBM_FP32 ? 20 : 32;
+  while (rows > 8 && strips * ((p.ny + rows - 1) / rows) < 4ll * cus) rows -= 4;
+  *ty = std::min(rows, p.ny);
+}
+
 lbm_status ensure_scratch(lbm_ctx* c) {
   if (c->work) return LBM_OK;
   const size_t n = (size_t)c->p.nx * c->p.ny;
@@ -380,8 +397,9 @@ lbm_status make_ctx(const lbm_params* p, void* stream, void* ba, void* bb, size_
   int tx, ty;
   default_launch(*p, &tx, &ty);
   set_geometry(c, tx, ty);
-  set_geometry2(c, p->nx >= 256 ? 256 : 128, std::min(64, p->ny));
-  c->fuse = 1;
+  default_launch2(*p, &tx, &ty);
+  set_geometry2(c, tx, ty);
+  c->fuse = 2;
   c->buf_bytes = 9 * (size_t)c->g.plane * elem_size(*p);
   c->step = 0;
   c->cur = 0;
@@ -544,18 +562,20 @@ void lbm_destroy(lbm_ctx* c) {
 
 lbm_status lbm_set_launch(lbm_ctx* c, const lbm_launch* l) {
   if (!c || !l) return fail(LBM_EINVAL, "NULL argument");
-  const int fuse = l->steps_per_pass == 0 ? 1 : l->steps_per_pass;
+  // steps_per_pass 0: two, unless the tile asked for is too narrow for them
+  const int fuse = l->steps_per_pass != 0 ? l->steps_per_pass : (l->tile_x == 64 ? 1 : 2);
   if (fuse != 1 && fuse != 2) return fail(LBM_EINVAL, "steps_per_pass %d not in {1, 2}", l->steps_per_pass);
   int tx = l->tile_x, ty = l->tile_y;
-  int dtx, dty;
+  int dtx, dty, dtx2, dty2;
   default_launch(c->p, &dtx, &dty);
+  default_launch2(c->p, &dtx2, &dty2);
   if (fuse == 1) {
     if (tx == 0) tx = dtx;
     if (ty == 0) ty = dty;
     if (tx != 64 && tx != 128 && tx != 256) return fail(LBM_EINVAL, "tile_x %d not in {64,128,256}", tx);
   } else {
-    if (tx == 0) tx = c->p.nx >= 256 ? 256 : 128;
-    if (ty == 0) ty = 64;
+    if (tx == 0) tx = dtx2;
+    if (ty == 0) ty = dty2;
     if (tx != 128 && tx != 256)
       return fail(LBM_EINVAL, "tile_x %d not in {128,256} for two steps per pass", tx);
   }
@@ -742,6 +762,9 @@ struct lbm_batch {
   hipStream_t stream = nullptr;
   int mode = LBM_BATCH_PER_STEP;
   int tile_x = 64, tile_y = 32;
+  int fuse = 1;                 // per-step mode: steps per launch (1 or 2)
+  void* d_tiles2 = nullptr;     // two-step tile list (fuse == 2)
+  int ntile2_total = 0;
   long long spin_limit = 1ll << 20;
   int per_cu = 0, cus = 0;
   // device layout
@@ -759,7 +782,7 @@ struct lbm_batch {
   int64_t step = 0;
   // graph cache
   hipGraphExec_t exec = nullptr;
-  int exec_mode = -1, exec_steps = 0, exec_parity = -1;
+  int exec_mode = -1, exec_steps = 0, exec_parity = -1, exec_fuse = 0;
   // FP64 scratch for observables / fields
   double* work = nullptr;
   double* partials = nullptr;
@@ -776,9 +799,9 @@ void batch_free_layout(lbm_batch* b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   b->exec = nullptr;
   b->exec_mode = -1;
-  for (void* q : {b->d_dom, b->d_tiles, (void*)b->d_group_begin})
+  for (void* q : {b->d_dom, b->d_tiles, b->d_tiles2, (void*)b->d_group_begin})
     if (q) (void)hipFree(q);
-  b->d_dom = b->d_tiles = nullptr;
+  b->d_dom = b->d_tiles = b->d_tiles2 = nullptr;
   b->d_group_begin = nullptr;
 }
 
@@ -844,6 +867,24 @@ lbm_status batch_layout(lbm_batch* b) {
     b->grid = b->ntile_total;
     group_begin.assign(2, 0);
   }
+  // two-step tiles (per-step mode with two steps per launch): strips of
+  // tile_x - 6 stored columns, the same row blocks
+  std::vector<unsigned char> ht2;
+  b->ntile2_total = 0;
+  if (b->mode == LBM_BATCH_PER_STEP && b->fuse == 2) {
+    const size_t tb2 = batch_tile_bytes();
+    const int w = b->tile_x - kStep2Halo;
+    for (int d = 0; d < b->n; ++d) {
+      const Geometry& g = b->g[d];
+      const int ns = (g.nx + w - 1) / w;
+      for (int rb = 0; rb < g.nrowblocks; ++rb)
+        for (int sx = 0; sx < ns; ++sx) {
+          ht2.resize(ht2.size() + tb2);
+          batch_fill_tile(d, sx * w, rb * g.tile_y, rb & 1, ht2.data() + ht2.size() - tb2);
+          ++b->ntile2_total;
+        }
+    }
+  }
   const size_t db = batch_domain_bytes(b->prec), tb = batch_tile_bytes();
   std::vector<unsigned char> hd(db * b->n), ht(tb * tiles.size());
   for (int d = 0; d < b->n; ++d)
@@ -856,6 +897,10 @@ lbm_status batch_layout(lbm_batch* b) {
   HIP_TRY(hipMalloc(&b->d_group_begin, group_begin.size() * sizeof(int)));
   HIP_TRY(hipMemcpyAsync(b->d_dom, hd.data(), hd.size(), hipMemcpyHostToDevice, b->stream));
   HIP_TRY(hipMemcpyAsync(b->d_tiles, ht.data(), ht.size(), hipMemcpyHostToDevice, b->stream));
+  if (!ht2.empty()) {
+    HIP_TRY(hipMalloc(&b->d_tiles2, ht2.size()));
+    HIP_TRY(hipMemcpyAsync(b->d_tiles2, ht2.data(), ht2.size(), hipMemcpyHostToDevice, b->stream));
+  }
   HIP_TRY(hipMemcpyAsync(b->d_group_begin, group_begin.data(), group_begin.size() * sizeof(int),
                          hipMemcpyHostToDevice, b->stream));
   HIP_TRY(hipStreamSynchronize(b->stream));
@@ -878,8 +923,15 @@ BatchRun batch_run(const lbm_batch* b, int nsteps, int parity) {
   return r;
 }
 
+// Launches that n steps take: one per step, or n / 2 two-step launches and a
+// single step for an odd n.
+int batch_launches(const lbm_batch* b, int n) {
+  return (b->mode == LBM_BATCH_PER_STEP && b->fuse == 2) ? n / 2 + n % 2 : n;
+}
+
 // Enqueues n steps: persistent = queue/counter reset, one launch and the
-// completion check; per-step = n launches with alternating buffers.
+// completion check; per-step = one launch per step (or per two steps) with
+// alternating buffers.
 hipError_t batch_enqueue(lbm_batch* b, int n) {
   hipError_t e = hipSuccess;
   if (b->mode == LBM_BATCH_PERSISTENT) {
@@ -887,18 +939,28 @@ hipError_t batch_enqueue(lbm_batch* b, int n) {
     e = launch_batch_reset(r, b->n, b->stream);
     if (e == hipSuccess) e = launch_batch(b->prec, b->eos, b->tile_x, true, r, b->stream);
     if (e == hipSuccess) e = launch_batch_check(b->prec, r, b->n, b->stream);
-  } else {
-    for (int s = 0; s < n && e == hipSuccess; ++s)
-      e = launch_batch(b->prec, b->eos, b->tile_x, false, batch_run(b, 1, (b->parity + s) & 1),
-                       b->stream);
+    return e;
   }
+  int launch = 0, left = n;
+  if (b->fuse == 2) {
+    for (; left >= 2 && e == hipSuccess; left -= 2, ++launch) {
+      BatchRun r = batch_run(b, 2, (b->parity + launch) & 1);
+      r.tiles = b->d_tiles2;
+      r.grid = b->ntile2_total;
+      e = launch_batch_step2(b->prec, b->eos, b->tile_x, r, b->stream);
+    }
+  }
+  for (; left > 0 && e == hipSuccess; --left, ++launch)
+    e = launch_batch(b->prec, b->eos, b->tile_x, false, batch_run(b, 1, (b->parity + launch) & 1),
+                     b->stream);
   return e;
 }
 
 // The same n steps captured once as a graph (re-captured when the mode, the
 // step count or the buffer parity changes).
 lbm_status batch_graph(lbm_batch* b, int n) {
-  if (b->exec && b->exec_mode == b->mode && b->exec_steps == n && b->exec_parity == b->parity)
+  if (b->exec && b->exec_mode == b->mode && b->exec_steps == n && b->exec_parity == b->parity &&
+      b->exec_fuse == b->fuse)
     return LBM_OK;
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   b->exec = nullptr;
@@ -916,6 +978,7 @@ lbm_status batch_graph(lbm_batch* b, int n) {
   b->exec_mode = b->mode;
   b->exec_steps = n;
   b->exec_parity = b->parity;
+  b->exec_fuse = b->fuse;
   return LBM_OK;
 }
 
@@ -1035,11 +1098,17 @@ lbm_status lbm_batch_set_launch(lbm_batch* b, const lbm_batch_launch* l) {
   if (l->mode == LBM_BATCH_PERSISTENT && !kPersistentEnabled)
     return fail(LBM_EINVAL, "persistent batch mode is switched off in this build (its kernel has not "
                             "passed on a GPU); use LBM_BATCH_PER_STEP");
-  const int tx = l->tile_x ? l->tile_x : 64, ty = l->tile_y ? l->tile_y : 32;
+  const int fuse = l->steps_per_pass ? l->steps_per_pass : 1;
+  if (fuse != 1 && fuse != 2) return fail(LBM_EINVAL, "steps_per_pass %d not in {1, 2}", fuse);
+  if (fuse == 2 && l->mode != LBM_BATCH_PER_STEP)
+    return fail(LBM_EINVAL, "two steps per launch needs the per-step mode");
+  const int tx = l->tile_x ? l->tile_x : (fuse == 2 ? 256 : 64), ty = l->tile_y ? l->tile_y : (fuse == 2 ? 16 : 32);
   if (tx != 64 && tx != 128 && tx != 256) return fail(LBM_EINVAL, "tile_x %d not in {64,128,256}", tx);
+  if (fuse == 2 && tx == 64) return fail(LBM_EINVAL, "tile_x 64 too narrow for two steps per launch");
   if (ty < 1) return fail(LBM_EINVAL, "tile_y %d < 1", ty);
   if (l->spin_limit < 0) return fail(LBM_EINVAL, "negative spin limit");
   b->mode = l->mode;
+  b->fuse = fuse;
   b->tile_x = tx;
   b->tile_y = ty;
   b->spin_limit = l->spin_limit ? l->spin_limit : (1ll << 20);
@@ -1057,6 +1126,11 @@ lbm_status lbm_batch_get_launch(const lbm_batch* b, lbm_batch_launch* l) {
   l->grid = b->grid;
   l->ntiles = b->ntile_total;
   l->resident_per_cu = b->per_cu;
+  l->steps_per_pass = b->fuse;
+  if (b->fuse == 2) {
+    l->grid = b->ntile2_total;
+    l->ntiles = b->ntile2_total;
+  }
   return LBM_OK;
 }
 
@@ -1102,7 +1176,7 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t n) {
     } else {
       HIP_TRY(batch_enqueue(b, k));
     }
-    b->parity = (b->parity + k) & 1;
+    b->parity = (b->parity + batch_launches(b, k)) & 1;
     left -= k;
   }
   b->step += n;

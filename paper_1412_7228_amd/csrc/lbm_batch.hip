@@ -25,6 +25,7 @@
 #include <vector>
 
 #include "lbm_tile.h"
+#include "lbm_tile2.h"
 
 namespace lbm {
 
@@ -142,6 +143,22 @@ __global__ void __launch_bounds__(BX)
   step_tile<T, EOS, BX, BIG>(D.f[parity], D.f[parity ^ 1], D.g, D.c, x0, y0, down != 0, ring);
 }
 
+// Per-step mode with two fused steps per launch: the tiles are strips of
+// BX - 6 stored columns (step2_tile).
+template <typename T, int EOS, int BX, bool BIG>
+__global__ void __launch_bounds__(BX)
+    k_batch_step2(const BatchDomain<T>* __restrict__ dom, const BatchTile* __restrict__ tiles,
+                  int parity) {
+  __shared__ Tile2Lds<T, BX> lds;
+  const int t = xcd_remap(blockIdx.x, gridDim.x);
+  const int d = __builtin_amdgcn_readfirstlane(tiles[t].domain);
+  const int x0 = __builtin_amdgcn_readfirstlane(tiles[t].x0);
+  const int y0 = __builtin_amdgcn_readfirstlane(tiles[t].y0);
+  const int down = __builtin_amdgcn_readfirstlane(tiles[t].down);
+  const BatchDomain<T>& D = dom[d];
+  step2_tile<T, EOS, BX, BIG>(D.f[parity], D.f[parity ^ 1], D.g, D.c, x0, y0, down != 0, lds);
+}
+
 __global__ void k_batch_reset(unsigned* done, int n, unsigned* head, int ngroups, int* err) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) done[i] = 0u;
@@ -223,6 +240,40 @@ hipError_t launch_batch(lbm_precision prec, int eos, int tile_x, bool persistent
                         hipStream_t s) {
   if (prec == LBM_FP32) return launch_t<float>(eos, tile_x, persistent, r, s);
   return launch_t<double>(eos, tile_x, persistent, r, s);
+}
+
+template <typename T, int EOS>
+static hipError_t launch_step2_e(int bx, const BatchRun& r, hipStream_t s) {
+  const BatchDomain<T>* d = static_cast<const BatchDomain<T>*>(r.dom);
+  const BatchTile* t = static_cast<const BatchTile*>(r.tiles);
+  switch (bx) {
+    case 128:
+      hipLaunchKernelGGL((k_batch_step2<T, EOS, 128, false>), dim3(r.grid), dim3(128), 0, s, d, t, r.parity);
+      break;
+    case 256:
+      hipLaunchKernelGGL((k_batch_step2<T, EOS, 256, false>), dim3(r.grid), dim3(256), 0, s, d, t, r.parity);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_step2_t(int eos, int bx, const BatchRun& r, hipStream_t s) {
+  switch (eos) {
+    case LBM_EOS_IDEAL: return launch_step2_e<T, LBM_EOS_IDEAL>(bx, r, s);
+    case LBM_EOS_CS: return launch_step2_e<T, LBM_EOS_CS>(bx, r, s);
+    case LBM_EOS_VDW: return launch_step2_e<T, LBM_EOS_VDW>(bx, r, s);
+    case LBM_EOS_PR: return launch_step2_e<T, LBM_EOS_PR>(bx, r, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_batch_step2(lbm_precision prec, int eos, int tile_x, const BatchRun& r,
+                              hipStream_t s) {
+  if (prec == LBM_FP32) return launch_step2_t<float>(eos, tile_x, r, s);
+  return launch_step2_t<double>(eos, tile_x, r, s);
 }
 
 hipError_t launch_batch_reset(const BatchRun& r, int ndomains, hipStream_t s) {

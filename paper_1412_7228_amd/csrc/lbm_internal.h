@@ -95,6 +95,9 @@ struct BatchRun {
 };
 hipError_t launch_batch(lbm_precision prec, int eos, int tile_x, bool persistent, const BatchRun& r,
                         hipStream_t s);
+// Per-step mode, two fused steps per launch over the two-step tile list.
+hipError_t launch_batch_step2(lbm_precision prec, int eos, int tile_x, const BatchRun& r,
+                              hipStream_t s);
 hipError_t launch_batch_reset(const BatchRun& r, int ndomains, hipStream_t s);
 hipError_t launch_batch_check(lbm_precision prec, const BatchRun& r, int ndomains, hipStream_t s);
 

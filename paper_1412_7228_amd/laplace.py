@@ -37,13 +37,13 @@ def initial_density(case: dict, cfg: dict) -> np.ndarray:
 
 
 def run_cases(cases: list, steps: int, precision: str = "fp32", mode: str = "per_step",
-              tile: tuple = (64, 32), chunk: int = 5000) -> list:
+              tile: tuple = (128, 16), chunk: int = 5000, steps_per_pass: int = 2) -> list:
     """Runs every case for `steps` steps in one batch; returns one result dict per case
     (the observables plus ``ok``: finite, positive densities, no U > 0 cell, a drop
     denser than its surroundings)."""
     cfgs = [case_config(c, precision) for c in cases]
     b = lbm.Batch(cfgs)
-    b.set_launch(mode, *tile)
+    b.set_launch(mode, *tile, steps_per_pass=steps_per_pass)
     for i, (c, cfg) in enumerate(zip(cases, cfgs)):
         b.init_field(i, initial_density(c, cfg))
     left = steps

@@ -73,7 +73,7 @@ class BatchLaunch(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32),
                 ("spin_limit", ctypes.c_int64), ("force_spin_limit", ctypes.c_int32),
                 ("grid", ctypes.c_int32), ("ntiles", ctypes.c_int32),
-                ("resident_per_cu", ctypes.c_int32)]
+                ("resident_per_cu", ctypes.c_int32), ("steps_per_pass", ctypes.c_int32)]
 
 
 BATCH_MODES = {"persistent": 0, "per_step": 1}
@@ -342,9 +342,9 @@ class Batch:
             pass
 
     def set_launch(self, mode: str = "per_step", tile_x: int = 0, tile_y: int = 0,
-                   spin_limit: int = 0, force_spin_limit: bool = False):
+                   spin_limit: int = 0, force_spin_limit: bool = False, steps_per_pass: int = 1):
         l = BatchLaunch(BATCH_MODES[mode], int(tile_x), int(tile_y), int(spin_limit),
-                        int(force_spin_limit), 0, 0, 0)
+                        int(force_spin_limit), 0, 0, 0, int(steps_per_pass))
         _check(self.lib.lbm_batch_set_launch(self.h, ctypes.byref(l)))
 
     @property
@@ -353,7 +353,8 @@ class Batch:
         _check(self.lib.lbm_batch_get_launch(self.h, ctypes.byref(l)))
         inv = {v: k for k, v in BATCH_MODES.items()}
         return dict(mode=inv[l.mode], tile_x=l.tile_x, tile_y=l.tile_y, spin_limit=l.spin_limit,
-                    grid=l.grid, ntiles=l.ntiles, resident_per_cu=l.resident_per_cu)
+                    grid=l.grid, ntiles=l.ntiles, resident_per_cu=l.resident_per_cu,
+                    steps_per_pass=l.steps_per_pass)
 
     def init_field(self, i: int, rho, ux=None, uy=None):
         shp = self.shapes[i]

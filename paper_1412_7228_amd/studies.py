@@ -42,9 +42,9 @@ def _finite(x):
     return float(x) if np.isfinite(x) else None
 
 
-def _run_batch(cfgs, rhos, steps, tile=(64, 16), chunk=5000):
+def _run_batch(cfgs, rhos, steps, tile=(128, 16), chunk=5000, steps_per_pass=2):
     b = lbm.Batch(cfgs)
-    b.set_launch("per_step", *tile)
+    b.set_launch("per_step", *tile, steps_per_pass=steps_per_pass)
     for i, r in enumerate(rhos):
         b.init_field(i, r)
     left = steps
@@ -68,7 +68,7 @@ def stable(o: dict, max_u: float = 0.1) -> bool:
 # ---------------------------------------------------------------------------
 def laplace_sweep(steps: int = 20000, precision: str = "fp32") -> dict:
     cases = laplace.sweep_cases(extra_A=(-0.9, (0.6,)))
-    res = laplace.run_cases(cases, steps, precision=precision, tile=(64, 16))
+    res = laplace.run_cases(cases, steps, precision=precision, tile=(128, 16))
     groups = {}
     for r in res:
         c = r["case"]
@@ -106,7 +106,7 @@ def a_sweep(As=None, steps: int = 20000, precision: str = "fp64") -> dict:
         flat = dict(cfg, ny=4)
         cfgs.append(flat)
         rhos.append(inputs.slab(100, 4, rl, rv, W=5.0))
-    obs = _run_batch(cfgs, rhos, steps, tile=(64, 16))
+    obs = _run_batch(cfgs, rhos, steps, tile=(128, 16))
     rows = []
     for i, A in enumerate(As):
         d, f = obs[2 * i], obs[2 * i + 1]
@@ -137,7 +137,7 @@ def stability_scan(As=(-0.5, 0.5), kappas=(0.0, 0.2, 0.5, 0.7, 0.9, 0.99), temps
                 cfgs.append(cfg)
                 rhos.append(r)
                 keys.append((A, k, T))
-    obs = _run_batch(cfgs, rhos, steps, tile=(64, 16))
+    obs = _run_batch(cfgs, rhos, steps, tile=(128, 16))
     table = {}
     for (A, k, T), o in zip(keys, obs):
         table.setdefault((A, k), []).append((T, stable(o), o))
@@ -163,7 +163,7 @@ def pr_laplace(kappas=(0.0, 0.9, 0.99), radii=(20, 25, 30, 35, 40), steps: int =
                precision: str = "fp64") -> dict:
     cases = [dict(n=120, R=R, kappa=k, seed=i, **PR_SEC4) for i, (k, R) in
              enumerate((k, R) for k in kappas for R in radii)]
-    res = laplace.run_cases(cases, steps, precision=precision, tile=(64, 16))
+    res = laplace.run_cases(cases, steps, precision=precision, tile=(128, 16))
     rows = []
     for k in kappas:
         rs = [r for r in res if r["case"]["kappa"] == k]

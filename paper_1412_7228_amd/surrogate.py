@@ -134,33 +134,38 @@ class Surrogate:
 # The study
 # ---------------------------------------------------------------------------
 def training_set(n_batches: int, seed: int, steps: int, side=(64, 512), domains: int = 256,
-                 log=print):
+                 r_range=(20.0, 60.0), log=print):
     """Droplets drawn as in the uneven batch (side, R = u * side, T/Tc, kappa, A),
     run in batches of `domains`; returns X [n, 3], Y [n, 3] of the runs that stayed
-    two-phase, and the count of draws outside the model's range."""
-    X, Y, bad = [], [], 0
+    two-phase with an equimolar radius in `r_range`, the count of draws outside the
+    model's range, and the count left out for their radius.  sigma = dp * R_e of
+    one drop depends on the drop's size (lattice effects below R ~ 20, slow
+    relaxation above R ~ 60), which three inputs cannot see."""
+    X, Y, bad, sized = [], [], 0, 0
     for bi in range(n_batches):
         draws = inputs.batch_draws(domains, seed + bi, side=side)
         cases = [dict(n=d["nx"], R=d["R"], T_over_Tc=d["T_over_Tc"], A=d["A"], kappa=d["kappa"],
                       seed=d["seed"]) for d in draws]
         t0 = time.time()
-        res = laplace.run_cases(cases, steps, precision="fp32", mode="per_step", tile=(64, 32))
+        res = laplace.run_cases(cases, steps, precision="fp32")
         for r in res:
             c = r["case"]
-            if r["ok"] and r["sigma"] > 0:
+            if not (r["ok"] and r["sigma"] > 0):
+                bad += 1
+            elif r_range is not None and not (r_range[0] <= r["R_e"] <= r_range[1]):
+                sized += 1
+            else:
                 X.append((c["A"], c["kappa"], c["T_over_Tc"]))
                 Y.append((r["sigma"], r["rho_in"], r["rho_out"]))
-            else:
-                bad += 1
         log(f"[surrogate] training batch {bi}: {sum(r['ok'] for r in res)}/{len(res)} two-phase, "
             f"{time.time() - t0:.1f} s")
-    return np.array(X), np.array(Y), bad
+    return np.array(X), np.array(Y), bad, sized
 
 
 def verify(specs, steps: int, n: int = 200, R: float = 40.0):
     """One LBM droplet run per (A, kappa, T/Tc) spec; returns sigma (nan if the run failed)."""
     cases = [dict(n=n, R=R, A=a, kappa=k, T_over_Tc=t, seed=i) for i, (a, k, t) in enumerate(specs)]
-    res = laplace.run_cases(cases, steps, precision="fp32", mode="per_step", tile=(64, 32))
+    res = laplace.run_cases(cases, steps, precision="fp32")
     return np.array([r["sigma"] if r["ok"] else np.nan for r in res])
 
 
@@ -168,11 +173,12 @@ def _num(x):
     return float(x) if np.isfinite(x) else None
 
 
-def study(seed: int = 0, n_targets: int = 64, train_batches: int = 2, train_steps: int = 60000,
+def study(seed: int = 0, n_targets: int = 64, train_batches: int = 4, train_steps: int = 60000,
           verify_steps: int = 20000, side=(64, 512), domains: int = 256, iters: int = 3000,
           lr: float = 1e-3, log=print) -> dict:
     t_start = time.time()
-    X, Y, bad = training_set(train_batches, seed, train_steps, side=side, domains=domains, log=log)
+    X, Y, bad, sized = training_set(train_batches, seed, train_steps, side=side, domains=domains,
+                                    log=log)
     surs, hists = {}, {}
     for name, prior in (("plain", False), ("eq28_prior", True)):
         surs[name] = Surrogate(seed=seed, prior_eq28=prior)
@@ -266,7 +272,8 @@ def study(seed: int = 0, n_targets: int = 64, train_batches: int = 2, train_step
         config=dict(seed=seed, n_targets=n_targets, train_batches=train_batches, domains=domains,
                     train_steps=train_steps, verify_steps=verify_steps, side=list(side),
                     verify_lattice=200, verify_radius=40, tolerance=TOLERANCE, iters=iters, lr=lr),
-        training=dict(samples=int(len(X)), outside_model_range=int(bad)),
+        training=dict(samples=int(len(X)), outside_model_range=int(bad), left_out_for_radius=int(sized),
+                      X=X.tolist(), Y=Y.tolist()),
         targets_valid=int(valid.sum()),
         surrogate=sur_rep["plain"],
         surrogate_eq28_prior=sur_rep["eq28_prior"],
@@ -284,7 +291,7 @@ def main():
     ap.add_argument("--out", default="surrogate_report.json")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--targets", type=int, default=64)
-    ap.add_argument("--train-batches", type=int, default=2)
+    ap.add_argument("--train-batches", type=int, default=4)
     ap.add_argument("--train-steps", type=int, default=60000,
                     help="steps of the training droplets (large drops relax slowly)")
     ap.add_argument("--verify-steps", type=int, default=20000)

@@ -62,14 +62,18 @@ def _rho0(i, d):
     return inputs.droplet(d["nx"], d["ny"], d["R"], rl, rv, W=4.0, noise=1e-2, seed=i)
 
 
-@pytest.mark.parametrize("mode", ["per_step",
+@pytest.mark.parametrize("mode", ["per_step", "per_step2",
                                   pytest.param("persistent", marks=pytest.mark.skip(reason=PERSISTENT_OFF))])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_batch_equals_single_lattices(lbm, mode, precision):
     say(f"batch {mode} {precision}")
     cfgs = _cfgs(precision)
     b = lbm.Batch(cfgs)
-    b.set_launch(mode, 64, 16)
+    if mode == "per_step2":  # two fused steps per launch; 7 and 30 steps end on single steps
+        b.set_launch("per_step", 128, 16, steps_per_pass=2)
+        assert b.launch["steps_per_pass"] == 2
+    else:
+        b.set_launch(mode, 64, 16)
     for i, d in enumerate(DOMAINS):
         b.init_field(i, _rho0(i, d))
     b.step(7)
@@ -171,3 +175,34 @@ def test_persistent_mode_is_rejected_while_switched_off(lbm):
         b.init_field(i, _rho0(i, d))
     b.step(3)
     b.sync()
+
+
+@pytest.mark.parametrize("tile", [(128, 8), (256, 16), (256, 13)])
+def test_two_step_batch_many_domains_equals_single_steps(lbm, tile):
+    """48 uneven domains, two fused steps per launch against one step per launch
+    (bitwise), over several calls with odd and even step counts."""
+    say(f"batch two-step many domains tile {tile}")
+    rng = np.random.default_rng(7)
+    e = th.carnahan_starling()
+    _, Tc = th.critical_point(e)
+    cfgs, rhos = [], []
+    for i in range(48):
+        nx, ny = int(rng.integers(12, 300)), int(rng.integers(12, 300))
+        T = float(rng.uniform(0.7, 0.85))
+        rv, rl = th.maxwell(e, T * Tc)
+        cfgs.append(dict(nx=nx, ny=ny, eos="cs", precision="fp32", T_over_Tc=T,
+                         A=float(rng.uniform(-0.7, -0.3)), kappa=float(rng.uniform(0.0, 0.8))))
+        rhos.append(inputs.droplet(nx, ny, max(1.0, 0.3 * min(nx, ny)), rl, rv, W=4.0, noise=1e-2,
+                                   seed=200 + i))
+    runs = {}
+    for spp in (1, 2):
+        b = lbm.Batch(cfgs)
+        b.set_launch("per_step", tile[0], tile[1], steps_per_pass=spp)
+        for i, r in enumerate(rhos):
+            b.init_field(i, r)
+        for k in (1, 64, 99, 100):
+            b.step(k)
+        b.sync()
+        runs[spp] = [b.f_soa(i) for i in range(len(cfgs))]
+    for i in range(len(cfgs)):
+        assert np.array_equal(runs[2][i], runs[1][i], equal_nan=True), i
