@@ -182,16 +182,17 @@ __device__ __forceinline__ void collide_cell(const T (&g)[9], T rho, const T (&U
   out[6] = b0 + (Yd - Xd) - Rq;
   out[7] = b0 - (Xd + Yd) + Rq;
   out[8] = b0 + (Xd - Yd) - Rq;
-  // f*_0 from the mass balance of the cell: the nine stored values then sum to
-  // the arriving density up to one rounding, so neither the rounded constants
-  // of M^{-1} nor the rounding of sums of nearly equal populations can create
-  // or destroy mass.  FP32 balances in FP64 (exact for nine FP32 values).
+  // f*_0 from the mass balance of the cell, so that neither the rounded
+  // constants of M^{-1} nor the rounding of sums of nearly equal populations
+  // create or destroy mass.  FP32 writes it as f*_0 = g_0 + sum_a (g_a - f*_a):
+  // the changes g_a - f*_a are small next to the populations (exact where they
+  // are within a factor 2 of each other), so the nine stored values sum to the
+  // arriving density up to about one rounding of f*_0, without bias (a plain
+  // FP32 rho - sum f*_a drifts by ~1e-9 of the mass per step).
   if constexpr (sizeof(T) == 4) {
-    const double rin = ((double)g[0] + (((double)g[1] + (double)g[3]) + ((double)g[2] + (double)g[4]))) +
-                       (((double)g[5] + (double)g[7]) + ((double)g[6] + (double)g[8]));
-    const double sout = (((double)out[1] + (double)out[2]) + ((double)out[3] + (double)out[4])) +
-                        (((double)out[5] + (double)out[6]) + ((double)out[7] + (double)out[8]));
-    out[0] = (T)(rin - sout);
+    const T d1 = g[1] - out[1], d2 = g[2] - out[2], d3 = g[3] - out[3], d4 = g[4] - out[4];
+    const T d5 = g[5] - out[5], d6 = g[6] - out[6], d7 = g[7] - out[7], d8 = g[8] - out[8];
+    out[0] = g[0] + (((d1 + d3) + (d2 + d4)) + ((d5 + d7) + (d6 + d8)));
   } else {
     out[0] = rho - (((out[1] + out[2]) + (out[3] + out[4])) + ((out[5] + out[6]) + (out[7] + out[8])));
   }
