@@ -10,14 +10,16 @@ streaming of one cell; the library's default launch fuses two time steps per
 kernel launch (each launch reads and writes the state once).
 
 Prints ONE JSON line:  value = MLUPS (million lattice updates per second).
-roofline = the bound of the dominant kernel: with two steps per launch the
-kernel is bound by vector ALU issue, so achieved = algorithmic FP operations
-(FLOPS_PER_LU per update, counted in the single-step kernel's gfx950 ISA, FMA
-= 2) per launch / measured launch time, against the FP32 (or FP64) vector
-peak without packed math; with one step per launch it is HBM-bound, and
-achieved = 72 B (FP32) / 144 B (FP64) per update / launch time, against
-8 TB/s.  cpu_baseline = the FP64 CPU oracle on the host cores on a bounded
-sample of the same lattice.
+roofline = the bound of the dominant kernel, HBM: with two steps per launch
+the state is read once and written once per launch, so the algorithmic bytes
+of a launch are 72 B (FP32) / 144 B (FP64) per cell; achieved = those bytes /
+the measured launch time, against 8 TB/s; traffic = the HBM bytes per launch
+that the FETCH_SIZE / WRITE_SIZE counters measured for this kernel in its
+default shape (halo re-reads included), null in any other shape.  The fields
+beside it give the same launch's vector-ALU view (FLOPS_PER_LU FP operations
+per update against the 78.6 TFLOP/s vector peak without packed math) and the
+bytes an unfused pair of single steps would have needed.  cpu_baseline = the
+FP64 CPU oracle on the host cores on a bounded sample of the same lattice.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -39,6 +41,9 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # the same for FP32 and FP64 on MI355X (packed FP32 is not used by this build)
 ALU_PEAK_TFLOPS = {"fp32": 78.6, "fp64": 78.6}
 FLOPS_PER_LU = 260  # FP arithmetic of one cell update in the single-step kernel's ISA
+# HBM bytes per launch of the two-step kernel in the default shape on 4096^2,
+# from rocprofv3 FETCH_SIZE + WRITE_SIZE (scaled by the copy calibration)
+MEASURED_TRAFFIC = {("fp32", 256, 16): (789.2e6 + 619.5e6), ("fp64", 256, 24): (1504.9e6 + 1218.2e6)}
 N = 4096
 RHO_MEAN = 0.183713  # (rho_v + rho_l)/2 of CS at 0.7Tc: (0.00929415 + 0.35813094)/2
 WORKLOAD = dict(nx=N, ny=N, eos="cs", T_over_Tc=0.7, A=-0.5, kappa=0.0)
@@ -116,13 +121,16 @@ def gpu_measure(precision, steps, warmup, tile):
     # bytes the launch must move: the state in and out once per launch
     gbs = BYTES_PER_LU[precision] * N * N / per_launch_s / 1e9
     tflops = FLOPS_PER_LU * N * N * spp / per_launch_s / 1e12
+    tx, ty = lat.launch[0], lat.launch[1]
+    traffic = MEASURED_TRAFFIC.get((precision, tx, ty)) if spp == 2 else None
+    roof = dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(gbs / HBM_PEAK_GBS, 4), traffic=traffic)
+    if traffic:
+        roof["traffic_gbs"] = round(traffic / per_launch_s / 1e9, 1)
     if spp == 2:
-        roof = dict(bound="alu", achieved=round(tflops, 2), peak=ALU_PEAK_TFLOPS[precision],
-                    unit="TFLOP/s", frac=round(tflops / ALU_PEAK_TFLOPS[precision], 4), traffic=None,
-                    hbm_gbs=round(gbs, 1))
-    else:
-        roof = dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(gbs / HBM_PEAK_GBS, 4), traffic=None)
+        roof.update(unfused_equivalent_gbs=round(gbs * 2, 1),
+                    alu=dict(achieved=round(tflops, 2), peak=ALU_PEAK_TFLOPS[precision], unit="TFLOP/s",
+                             frac=round(tflops / ALU_PEAK_TFLOPS[precision], 4)))
     res = dict(ms_per_step=ms / steps, mlups=lus / (ms * 1e-3) / 1e6, steps=steps,
                launch_ms=per_launch_s * 1e3, roofline=roof, tile=list(lat.launch), mass=ob["mass"],
                n_nonfinite=ob["n_nonfinite"])

@@ -358,7 +358,7 @@ void default_launch(const lbm_params& p, int* tx, int* ty) {
 }
 
 // Default shape of the two-step launch: 256-lane strips (250 stored columns)
-// where the lattice is that wide, else 128; 20 rows (FP32) or 32 rows (FP64)
+// where the lattice is that wide, else 128; 16 rows (FP32) or 24 rows (FP64)
 // per workgroup, fewer while that leaves under 4 workgroups per CU.  (On the
 // 4096^2 lattice 14 to 28 rows are within 1.5% of each other in FP32, 16 to 32
 // in FP64; 8 rows lose 12%, 64 rows 15% from the tail of the grid.)
@@ -369,7 +369,7 @@ void default_launch2(const lbm_params& p, int* tx, int* ty) {
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
     cus = 256;
   const long long strips = (p.nx + *tx - kStep2Halo - 1) / (*tx - kStep2Halo);
-  int rows = p.precision == LBM_FP32 ? 20 : 32;
+  int rows = p.precision == LBM_FP32 ? 16 : 24;
   while (rows > 8 && strips * ((p.ny + rows - 1) / rows) < 4ll * cus) rows -= 4;
   *ty = std::min(rows, p.ny);
 }

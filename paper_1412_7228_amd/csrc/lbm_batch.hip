@@ -146,7 +146,7 @@ __global__ void __launch_bounds__(BX)
 // Per-step mode with two fused steps per launch: the tiles are strips of
 // BX - 6 stored columns (step2_tile).
 template <typename T, int EOS, int BX, bool BIG>
-__global__ void __launch_bounds__(BX)
+__global__ void __launch_bounds__(BX, sizeof(T) == 4 ? 5 : 1)
     k_batch_step2(const BatchDomain<T>* __restrict__ dom, const BatchTile* __restrict__ tiles,
                   int parity) {
   __shared__ Tile2Lds<T, BX> lds;
@@ -156,7 +156,10 @@ __global__ void __launch_bounds__(BX)
   const int y0 = __builtin_amdgcn_readfirstlane(tiles[t].y0);
   const int down = __builtin_amdgcn_readfirstlane(tiles[t].down);
   const BatchDomain<T>& D = dom[d];
-  step2_tile<T, EOS, BX, BIG>(D.f[parity], D.f[parity ^ 1], D.g, D.c, x0, y0, down != 0, lds);
+  if (down)
+    step2_tile<T, EOS, BX, BIG, true>(D.f[parity], D.f[parity ^ 1], D.g, D.c, x0, y0, lds);
+  else
+    step2_tile<T, EOS, BX, BIG, false>(D.f[parity], D.f[parity ^ 1], D.g, D.c, x0, y0, lds);
 }
 
 __global__ void k_batch_reset(unsigned* done, int n, unsigned* head, int ngroups, int* err) {

@@ -62,16 +62,21 @@ static hipError_t launch_step_p(const Geometry& g, const ModelConsts& m, const v
 }
 
 // Two fused steps over the whole lattice; the same workgroup-to-tile order.
+// FP32: at most 102 VGPRs, so that 5 workgroups of 256 lanes (31 KB of LDS
+// each) fit on a CU.
 template <typename T, int EOS, int BX, bool BIG>
-__global__ void __launch_bounds__(BX) k_step2(const T* __restrict__ fa, T* __restrict__ fb,
+__global__ void __launch_bounds__(BX, sizeof(T) == 4 ? 5 : 1) k_step2(const T* __restrict__ fa, T* __restrict__ fb,
                                                const Geometry geo, const DevC<T> c) {
   __shared__ Tile2Lds<T, BX> lds;
   static_assert(tile2_width<BX>() == BX - kStep2Halo, "strip width");
   const int lb = xcd_remap(blockIdx.x, geo.nblocks);
   const int rb = lb / geo.nstrips;
   const int strip = lb - rb * geo.nstrips;
-  step2_tile<T, EOS, BX, BIG>(fa, fb, geo, c, strip * tile2_width<BX>(), rb * geo.tile_y,
-                              (rb & 1) != 0, lds);
+  const int xs = strip * tile2_width<BX>(), y0 = rb * geo.tile_y;
+  if (rb & 1)
+    step2_tile<T, EOS, BX, BIG, true>(fa, fb, geo, c, xs, y0, lds);
+  else
+    step2_tile<T, EOS, BX, BIG, false>(fa, fb, geo, c, xs, y0, lds);
 }
 
 template <typename T, int EOS, bool BIG>
