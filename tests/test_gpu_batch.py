@@ -177,11 +177,12 @@ def test_persistent_mode_is_rejected_while_switched_off(lbm):
     b.sync()
 
 
-@pytest.mark.parametrize("tile", [(128, 8), (256, 16), (256, 13)])
-def test_two_step_batch_many_domains_equals_single_steps(lbm, tile):
+@pytest.mark.parametrize("tile,precision", [((128, 8), "fp32"), ((256, 16), "fp32"), ((256, 13), "fp32"),
+                                            ((128, 16), "fp64")])
+def test_two_step_batch_many_domains_equals_single_steps(lbm, tile, precision):
     """48 uneven domains, two fused steps per launch against one step per launch
     (bitwise), over several calls with odd and even step counts."""
-    say(f"batch two-step many domains tile {tile}")
+    say(f"batch two-step many domains tile {tile} {precision}")
     rng = np.random.default_rng(7)
     e = th.carnahan_starling()
     _, Tc = th.critical_point(e)
@@ -190,7 +191,7 @@ def test_two_step_batch_many_domains_equals_single_steps(lbm, tile):
         nx, ny = int(rng.integers(12, 300)), int(rng.integers(12, 300))
         T = float(rng.uniform(0.7, 0.85))
         rv, rl = th.maxwell(e, T * Tc)
-        cfgs.append(dict(nx=nx, ny=ny, eos="cs", precision="fp32", T_over_Tc=T,
+        cfgs.append(dict(nx=nx, ny=ny, eos="cs", precision=precision, T_over_Tc=T,
                          A=float(rng.uniform(-0.7, -0.3)), kappa=float(rng.uniform(0.0, 0.8))))
         rhos.append(inputs.droplet(nx, ny, max(1.0, 0.3 * min(nx, ny)), rl, rv, W=4.0, noise=1e-2,
                                    seed=200 + i))

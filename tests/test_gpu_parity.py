@@ -289,6 +289,10 @@ TWO_STEP_CASES = [
     (1000, 130, dict(eos="pr", K=0.5, T_over_Tc=0.8, A=-0.3, kappa=0.5), 128, 32, 12),
     (122, 122, dict(eos="ideal", A=-0.5, kappa=0.2), 128, 64, 6),
     (501, 77, dict(eos="cs", T_over_Tc=0.75, A=-0.4, kappa=0.6, nu_gas=0.2, nu_liquid=0.1), 256, 16, 11),
+    # lattices narrower than the 3-column halo of a strip, and a single column of strips
+    (3, 3, dict(eos="cs", T_over_Tc=0.8, A=-0.5, kappa=0.2), 128, 16, 5),
+    (5, 4, dict(eos="vdw", K=0.3, T_over_Tc=0.9, A=0.3, kappa=0.5), 256, 3, 8),
+    (7, 250, dict(eos="cs", T_over_Tc=0.8, A=-0.5, kappa=0.0), 128, 64, 10),
 ]
 
 
