@@ -74,10 +74,16 @@ __device__ __forceinline__ void step2_tile(const T* __restrict__ fa, T* __restri
   constexpr int AH0 = DOWN ? 2 : 4, AH1 = DOWN ? 5 : 8, AH2 = DOWN ? 6 : 7;  // shifts 0, -1, +1
   constexpr int BH0 = DOWN ? 4 : 2, BH1 = DOWN ? 8 : 5, BH2 = DOWN ? 7 : 6;  // shifts 0, -1, +1
 
+  // rows y0 - 4 .. y0 + H + 3 are gathered: more than one period away from the
+  // lattice when ny < 4, so the wrap is a full modulo (uniform, scalar ALU)
+  auto wrap_row = [&](int v) {
+    const int m = v % ny;
+    return m < 0 ? m + ny : m;
+  };
   auto gather_row = [&](int r, T(&g)[9]) {
-    const unsigned rr = wrap_(r, ny) * row_bytes;
-    const unsigned rm = wrap_(r - 1, ny) * row_bytes;
-    const unsigned rp = wrap_(r + 1, ny) * row_bytes;
+    const unsigned rr = wrap_row(r) * row_bytes;
+    const unsigned rm = wrap_row(r - 1) * row_bytes;
+    const unsigned rp = wrap_row(r + 1) * row_bytes;
     gather(pa, rr, rm, rp, ox, oxm, oxp, g);
   };
   // stencil of the centre row (slot s_mid) from the rows before (s_old) and
