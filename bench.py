@@ -43,7 +43,7 @@ ALU_PEAK_TFLOPS = {"fp32": 78.6, "fp64": 78.6}
 FLOPS_PER_LU = 260  # FP arithmetic of one cell update in the single-step kernel's ISA
 # HBM bytes per launch of the two-step kernel in the default shape on 4096^2,
 # from rocprofv3 FETCH_SIZE + WRITE_SIZE (scaled by the copy calibration)
-MEASURED_TRAFFIC = {("fp32", 256, 16): (789.2e6 + 619.5e6), ("fp64", 256, 24): (1504.9e6 + 1218.2e6)}
+MEASURED_TRAFFIC = {("fp32", 256, 16): (788.7e6 + 619.2e6), ("fp64", 256, 24): (1504.4e6 + 1218.2e6)}
 N = 4096
 RHO_MEAN = 0.183713  # (rho_v + rho_l)/2 of CS at 0.7Tc: (0.00929415 + 0.35813094)/2
 WORKLOAD = dict(nx=N, ny=N, eos="cs", T_over_Tc=0.7, A=-0.5, kappa=0.0)

@@ -219,7 +219,8 @@ typedef enum {
 
 typedef struct {
   int32_t mode;             /* lbm_batch_mode                                         */
-  int32_t tile_x, tile_y;   /* tile of every domain; 0 = default (64 x 32)            */
+  int32_t tile_x, tile_y;   /* tile of every domain; 0 = default (128 x 16 with two
+                               steps per launch, 64 x 32 with one)                   */
   int64_t spin_limit;       /* persistent mode: polls before a barrier wait gives up;
                                0 = default (2^20, about a second)                      */
   int32_t force_spin_limit; /* non-zero with spin_limit 0: use 0 (test of the abort path) */
@@ -230,7 +231,8 @@ typedef struct {
   /* input again: */
   int32_t steps_per_pass;   /* per-step mode: 1, or 2 = two fused steps per launch as in
                                lbm_launch (tile_x in {128, 256}; an odd count ends with
-                               one single-step launch); 0 = 1                          */
+                               one single-step launch); 0 = 2 in the per-step mode unless
+                               tile_x is 64, else 1                                     */
 } lbm_batch_launch;
 
 /* Creates a batch of n domains with parameters params[0..n).  Allocates one
@@ -239,7 +241,8 @@ typedef struct {
  * counter reset + launch, or chunks of up to 64 per-step launches), on the
  * null stream as plain launches.
  * LBM_EINVAL if a domain's parameters are invalid or the EOS kinds or
- * precisions differ. Default launch: LBM_BATCH_PER_STEP, 64 x 32 tiles. */
+ * precisions differ. Default launch: LBM_BATCH_PER_STEP with two steps per
+ * launch, 128 x 16 tiles. */
 lbm_status lbm_batch_create(const lbm_params* params, int32_t n, void* hip_stream, lbm_batch** out);
 void lbm_batch_destroy(lbm_batch* b);
 

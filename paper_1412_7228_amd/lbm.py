@@ -342,7 +342,7 @@ class Batch:
             pass
 
     def set_launch(self, mode: str = "per_step", tile_x: int = 0, tile_y: int = 0,
-                   spin_limit: int = 0, force_spin_limit: bool = False, steps_per_pass: int = 1):
+                   spin_limit: int = 0, force_spin_limit: bool = False, steps_per_pass: int = 0):
         l = BatchLaunch(BATCH_MODES[mode], int(tile_x), int(tile_y), int(spin_limit),
                         int(force_spin_limit), 0, 0, 0, int(steps_per_pass))
         _check(self.lib.lbm_batch_set_launch(self.h, ctypes.byref(l)))
