@@ -405,11 +405,11 @@ lbm_status make_ctx(const lbm_params* p, void* stream, void* ba, void* bb, size_
   c->cur = 0;
   c->stream = static_cast<hipStream_t>(stream);  // NULL is the HIP null stream
   c->own_stream = false;
+  const size_t need = c->buf_bytes;  // read before any lbm_destroy(c) below
   if (ba) {
-    if (!bb || bytes < c->buf_bytes || ((uintptr_t)ba & 255) || ((uintptr_t)bb & 255)) {
+    if (!bb || bytes < need || ((uintptr_t)ba & 255) || ((uintptr_t)bb & 255)) {
       lbm_destroy(c);
-      return fail(LBM_EINVAL, "caller buffers: need two 256-byte aligned buffers of %zu bytes",
-                  c->buf_bytes);
+      return fail(LBM_EINVAL, "caller buffers: need two 256-byte aligned buffers of %zu bytes", need);
     }
     c->buf[0] = ba; c->buf[1] = bb; c->own_buf = false;
   } else {
@@ -418,8 +418,8 @@ lbm_status make_ctx(const lbm_params* p, void* stream, void* ba, void* bb, size_
       hipError_t e = hipMalloc(&c->buf[i], c->buf_bytes);
       if (e != hipSuccess) {
         lbm_destroy(c);
-        return fail(e == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE, "hipMalloc(%zu): %s",
-                    c->buf_bytes, hipGetErrorString(e));
+        return fail(e == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE, "hipMalloc(%zu): %s", need,
+                    hipGetErrorString(e));
       }
     }
   }
@@ -999,7 +999,8 @@ lbm_status batch_scratch(lbm_batch* b) {
 lbm_status batch_check_error(lbm_batch* b) {
   HIP_TRY(hipStreamSynchronize(b->stream));
   int err = 0;
-  HIP_TRY(hipMemcpy(&err, b->d_err, sizeof err, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpyAsync(&err, b->d_err, sizeof err, hipMemcpyDeviceToHost, b->stream));
+  HIP_TRY(hipStreamSynchronize(b->stream));
   if (err) {
     // reported once; the state of an aborted launch is not a whole step
     HIP_TRY(hipMemsetAsync(b->d_err, 0, sizeof(int), b->stream));

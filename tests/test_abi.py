@@ -102,3 +102,20 @@ def test_library_coexistence_matches_oracle_maxwell(lib, oracle_mod, eos, tr):
 def test_coexistence_rejects_supercritical(lib):
     with pytest.raises(lbm.LBMError):
         lbm.coexistence(dict(eos="cs", T_over_Tc=1.05))
+
+
+@pytest.mark.parametrize("offset,nbytes", [(8, None), (0, 16)])
+def test_caller_buffers_misaligned_or_short_are_rejected(lib, offset, nbytes):
+    """lbm_create_ext checks the caller's buffers before any device call: a
+    pointer that is not 256-byte aligned, or a size below lbm_buffer_bytes, is
+    LBM_EINVAL and the error text names the bytes needed."""
+    p = lbm.make_params(dict(nx=16, ny=16))
+    need = lib.lbm_buffer_bytes(ctypes.byref(p))
+    host = (ctypes.c_char * (2 * need + 1024))()
+    base = (ctypes.addressof(host) + 255) // 256 * 256
+    a, b = base + offset, base + need + 256
+    h = ctypes.c_void_p()
+    rc = lib.lbm_create_ext(ctypes.byref(p), None, ctypes.c_void_p(a), ctypes.c_void_p(b),
+                            need if nbytes is None else nbytes, ctypes.byref(h))
+    assert rc == -1 and not h.value
+    assert str(need).encode() in lib.lbm_last_error()
