@@ -18,8 +18,11 @@ that the FETCH_SIZE / WRITE_SIZE counters measured for this kernel in its
 default shape (halo re-reads included), null in any other shape.  The fields
 beside it give the same launch's vector-ALU view (FLOPS_PER_LU FP operations
 per update against the 78.6 TFLOP/s vector peak without packed math) and the
-bytes an unfused pair of single steps would have needed.  cpu_baseline = the
-FP64 CPU oracle on the host cores on a bounded sample of the same lattice.
+bytes an unfused pair of single steps would have needed.  slab_share = the same
+kernel on one GPU's share of the lattice cut into 8 y-slabs (4096 x 512 rows
+plus 4 ghost rows per side), and the cost of refreshing the ghost rows.
+cpu_baseline = the FP64 CPU oracle on the host cores on a bounded sample of the
+same lattice.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -57,6 +60,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--fp64-steps", type=int, default=500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-slab", action="store_true", help="skip the one-GPU slab share measurement")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--tile", type=str, default="", help="tile_x,tile_y of the step kernel")
     ap.add_argument("--copy-mib", type=int, default=1024,
@@ -138,6 +142,55 @@ def gpu_measure(precision, steps, warmup, tile):
     return res
 
 
+def slab_share(launches=400, slabs=8, tiles=((0, 0), (128, 16), (256, 8), (128, 8))):
+    """One GPU's share of the same lattice cut into `slabs` y-slabs: a 4096 x (4096/slabs)
+    slab plus 4 ghost rows on each side, advanced with two steps per launch over its
+    interior rows (lbm_step_rows).  Times the launches alone (per launch shape) and the
+    ghost-row refresh (two copies of 9 planes x 4 rows, the bytes a neighbour would
+    send) alone; the two are serial here."""
+    import torch
+    from paper_1412_7228_amd import inputs, lbm
+
+    h, g = N // slabs, 4
+    lat = lbm.Lattice(dict(WORKLOAD, ny=h + 2 * g, precision="fp32"))
+    lat.init_field(inputs.spinodal(N, h + 2 * g, RHO_MEAN, noise=1e-2, seed=0))
+    s = lat.stream
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    shapes = []
+    for tx, ty in tiles:
+        lat.set_launch(tx, ty, 2)
+        for _ in range(20):
+            lat.step_rows(2, g, h)
+        torch.cuda.synchronize()
+        t0, t1 = ev(), ev()
+        t0.record(s)
+        for _ in range(launches):
+            lat.step_rows(2, g, h)
+        t1.record(s)
+        torch.cuda.synchronize()
+        us = t0.elapsed_time(t1) * 1e3 / launches
+        shapes.append(dict(tile=list(lat.launch[:2]), launch_us=round(us, 2),
+                           mlups=round(2 * N * h / us, 1)))
+    best = min(shapes, key=lambda r: r["launch_us"])
+    cur = lat.state_tensor()
+    with torch.cuda.stream(s):
+        t0, t1 = ev(), ev()
+        t0.record(s)
+        for _ in range(launches):
+            cur[:, :g] = cur[:, h:h + g]
+            cur[:, h + g:] = cur[:, g:2 * g]
+        t1.record(s)
+    torch.cuda.synchronize()
+    ex_us = t0.elapsed_time(t1) * 1e3 / launches
+    ob = lat.observables(check=False)
+    lat.close()
+    halo_bytes = 2 * 9 * g * N * 4
+    return dict(slab=[N, h], ghost_rows=g, shapes=shapes, best=best, exchange_us=round(ex_us, 2),
+                exchange_bytes=halo_bytes,
+                mlups_with_exchange=round(2 * N * h / (best["launch_us"] + ex_us), 1),
+                n_nonfinite=ob["n_nonfinite"])
+
+
 def cpu_baseline(seconds):
     """The FP64 oracle (as it stands) on the full 4096^2 input, all host cores, as many
     whole steps as fit in about `seconds`."""
@@ -179,6 +232,11 @@ def main():
         print(f"[bench] fp64 {N}x{N}: timed {a.fp64_steps}", file=sys.stderr, flush=True)
         r64 = gpu_measure("fp64", a.fp64_steps, max(10, a.warmup // 4), tile)
         print(f"[bench] fp64 {r64}", file=sys.stderr, flush=True)
+    slab = None
+    if not a.no_slab:
+        print("[bench] slab share (8 y-slabs)", file=sys.stderr, flush=True)
+        slab = slab_share()
+        print(f"[bench] slab {slab}", file=sys.stderr, flush=True)
     copy = None
     if a.copy_mib > 0:
         copy = copy_bandwidth(a.copy_mib)
@@ -214,6 +272,7 @@ def main():
                                                           "steps_per_pass": r64["tile"][2]},
             "roofline": r64["roofline"],
         },
+        "slab_share": slab,
         "cpu_baseline": cpu,
         "copy_ceiling": None if copy is None else {
             "gbs": round(copy["gbs"], 1), "bytes": copy["bytes_per_copy"],

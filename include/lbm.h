@@ -179,6 +179,21 @@ lbm_status lbm_set_distributions(lbm_ctx* ctx, const double* f);
 /* Enqueues n >= 0 time steps on the context stream and returns. */
 lbm_status lbm_step(lbm_ctx* ctx, int64_t n);
 
+/* One launch of the same time step (Eqs. 1, 9, 23, 25) that updates only the
+ * rows [y_begin, y_begin + rows) of the lattice: n = 1 step, or n = 2 steps
+ * when the context runs two steps per pass (lbm_launch.steps_per_pass).  The
+ * launch reads the current state's rows within 2n of the range (periodic in
+ * y, as lbm_step) and writes the range into the other buffer, which then
+ * becomes current; rows outside the range keep whatever that buffer held
+ * (the state of an earlier launch).  The paper's lattice is one periodic
+ * domain; this entry point is what a y-slab decomposition of it needs: a slab
+ * of h rows is a context of h + 4n rows whose first and last 2n rows are
+ * ghost rows, updated with (n, 2n, h) and refreshed from the neighbouring
+ * slabs' current buffers (lbm_state_info) before the next call.  LBM_EINVAL
+ * for n outside {1, 2}, n = 2 with one step per pass, rows < 1 or a range
+ * outside [0, ny); LBM_ESTATE before the state is initialised. */
+lbm_status lbm_step_rows(lbm_ctx* ctx, int32_t n, int32_t y_begin, int32_t rows);
+
 /* Computes the observables in FP64 on the device (deterministic reduction
  * order), synchronises and fills *out.  Returns LBM_ENONFINITE or
  * LBM_EDOMAIN (after filling *out) if the state holds such cells. */
@@ -298,7 +313,8 @@ lbm_status lbm_mlp_forward(lbm_mlp* m, const float* x, int32_t n, float* y);
  * inputs (dx, n x 3).  Either output may be NULL. */
 lbm_status lbm_mlp_backward(lbm_mlp* m, const float* x, const float* dy, int32_t n, float* grad,
                             float* dx);
-/* Training set (n <= max_batch) kept on the device. */
+/* Training set (n <= max_batch) kept on the device in buffers of its own:
+ * lbm_mlp_forward and lbm_mlp_backward between training calls leave it as set. */
 lbm_status lbm_mlp_set_data(lbm_mlp* m, const float* x, const float* t, int32_t n);
 /* iters full-batch Adam steps with learning rate lr; loss_out (iters values,
  * may be NULL) receives the loss before each step. */

@@ -329,6 +329,8 @@ Geometry make_geometry(const lbm_params& p, int tile_x, int tile_y, int width) {
   g.nstrips = (g.nx + width - 1) / width;
   g.nrowblocks = (g.ny + tile_y - 1) / tile_y;
   g.nblocks = g.nstrips * g.nrowblocks;
+  g.y_begin = 0;
+  g.y_end = g.ny;
   return g;
 }
 
@@ -658,6 +660,29 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
                         c->buf[1 - c->cur], c->stream));
     c->cur = 1 - c->cur;
   }
+  c->step += n;
+  return LBM_OK;
+}
+
+lbm_status lbm_step_rows(lbm_ctx* c, int32_t n, int32_t y_begin, int32_t rows) {
+  if (!c) return fail(LBM_EINVAL, "NULL context");
+  if (!c->initialized) return fail(LBM_ESTATE, "lbm_step_rows before lbm_init_field");
+  if (n != 1 && !(n == 2 && c->fuse == 2))
+    return fail(LBM_EINVAL, "lbm_step_rows: n = %d; one launch does 1 step, or 2 with two steps per pass", n);
+  if (rows < 1 || y_begin < 0 || (int64_t)y_begin + rows > c->p.ny)
+    return fail(LBM_EINVAL, "lbm_step_rows: rows [%d, %lld) outside [0, %d)", y_begin,
+                (long long)y_begin + rows, c->p.ny);
+  Geometry g = n == 2 ? c->g2 : c->g;
+  g.y_begin = y_begin;
+  g.y_end = y_begin + rows;
+  g.nrowblocks = (rows + g.tile_y - 1) / g.tile_y;
+  g.nblocks = g.nstrips * g.nrowblocks;
+  const lbm_precision prec = (lbm_precision)c->p.precision;
+  if (n == 2)
+    HIP_TRY(launch_step2(prec, g, c->m, c->buf[c->cur], c->buf[1 - c->cur], c->stream));
+  else
+    HIP_TRY(launch_step(prec, g, c->m, c->buf[c->cur], c->buf[1 - c->cur], c->stream));
+  c->cur = 1 - c->cur;
   c->step += n;
   return LBM_OK;
 }
@@ -1045,6 +1070,8 @@ lbm_status lbm_batch_create(const lbm_params* params, int32_t n, void* hip_strea
     Geometry& g = b->g[d];
     g.nx = params[d].nx;
     g.ny = params[d].ny;
+    g.y_begin = 0;
+    g.y_end = g.ny;
     g.pitch = pitch_of(params[d]);
     g.plane = (long long)g.ny * g.pitch;
     const size_t bytes = (9 * (size_t)g.plane * es + 255) / 256 * 256;
@@ -1227,7 +1254,8 @@ struct lbm_mlp {
   hipStream_t stream = nullptr;
   float *p = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr, *gpart = nullptr;
   unsigned short* wb = nullptr;
-  float *x = nullptr, *t = nullptr, *y = nullptr, *dy = nullptr, *acts = nullptr, *dx = nullptr;
+  float *x = nullptr, *y = nullptr, *dy = nullptr, *acts = nullptr, *dx = nullptr;
+  float *xd = nullptr, *td = nullptr;  // the training set of lbm_mlp_set_data (never reused as scratch)
   float* loss = nullptr;
   int loss_cap = 0;
   int ndata = 0;
@@ -1265,7 +1293,8 @@ lbm_status lbm_mlp_create(int32_t max_batch, void* hip_stream, lbm_mlp** out) {
   alloc((void**)&m->gpart, (size_t)nwg * np * 4);
   alloc((void**)&m->wb, np * 2);
   alloc((void**)&m->x, (size_t)max_batch * 3 * 4);
-  alloc((void**)&m->t, (size_t)max_batch * 3 * 4);
+  alloc((void**)&m->xd, (size_t)max_batch * 3 * 4);
+  alloc((void**)&m->td, (size_t)max_batch * 3 * 4);
   alloc((void**)&m->y, (size_t)max_batch * 3 * 4);
   alloc((void**)&m->dy, (size_t)max_batch * 3 * 4);
   alloc((void**)&m->dx, (size_t)max_batch * 3 * 4);
@@ -1286,7 +1315,7 @@ void lbm_mlp_destroy(lbm_mlp* m) {
   if (!m) return;
   (void)hipStreamSynchronize(m->stream);
   for (void* q : {(void*)m->p, (void*)m->m, (void*)m->v, (void*)m->grad, (void*)m->gpart, (void*)m->wb,
-                  (void*)m->x, (void*)m->t, (void*)m->y, (void*)m->dy, (void*)m->dx, (void*)m->acts,
+                  (void*)m->x, (void*)m->xd, (void*)m->td, (void*)m->y, (void*)m->dy, (void*)m->dx, (void*)m->acts,
                   (void*)m->loss})
     if (q) (void)hipFree(q);
   delete m;
@@ -1341,8 +1370,8 @@ lbm_status lbm_mlp_set_data(lbm_mlp* m, const float* x, const float* t, int32_t 
   if (!m || !x || !t) return fail(LBM_EINVAL, "NULL argument");
   lbm_status st = mlp_check_n(m, n);
   if (st != LBM_OK) return st;
-  HIP_TRY(hipMemcpyAsync(m->x, x, (size_t)n * 12, hipMemcpyHostToDevice, m->stream));
-  HIP_TRY(hipMemcpyAsync(m->t, t, (size_t)n * 12, hipMemcpyHostToDevice, m->stream));
+  HIP_TRY(hipMemcpyAsync(m->xd, x, (size_t)n * 12, hipMemcpyHostToDevice, m->stream));
+  HIP_TRY(hipMemcpyAsync(m->td, t, (size_t)n * 12, hipMemcpyHostToDevice, m->stream));
   HIP_TRY(hipStreamSynchronize(m->stream));
   m->ndata = n;
   return LBM_OK;
@@ -1362,9 +1391,9 @@ lbm_status lbm_mlp_train(lbm_mlp* m, int32_t iters, float lr, float* loss_out) {
   for (int it = 0; it < iters; ++it) {
     ++m->adam_t;
     const float c1 = 1.f - std::pow(b1, (float)m->adam_t), c2 = 1.f - std::pow(b2, (float)m->adam_t);
-    HIP_TRY(launch_mlp_forward(m->x, m->ndata, m->p, m->wb, m->acts, m->y, m->stream));
-    HIP_TRY(launch_mlp_mse(m->y, m->t, m->ndata, m->dy, m->loss + it, m->stream));
-    HIP_TRY(launch_mlp_backward(m->x, m->acts, m->dy, m->ndata, m->wb, m->gpart, m->grad, nullptr, m->stream));
+    HIP_TRY(launch_mlp_forward(m->xd, m->ndata, m->p, m->wb, m->acts, m->y, m->stream));
+    HIP_TRY(launch_mlp_mse(m->y, m->td, m->ndata, m->dy, m->loss + it, m->stream));
+    HIP_TRY(launch_mlp_backward(m->xd, m->acts, m->dy, m->ndata, m->wb, m->gpart, m->grad, nullptr, m->stream));
     HIP_TRY(launch_mlp_adam(m->p, m->m, m->v, m->grad, m->wb, lr, b1, b2, eps, c1, c2, m->stream));
   }
   if (loss_out && iters > 0)

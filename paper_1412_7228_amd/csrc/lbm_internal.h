@@ -15,8 +15,9 @@ struct Geometry {
   int nx, ny, pitch;       // elements; pitch = row stride of one plane
   long long plane;         // ny * pitch elements
   int tile_x, tile_y;      // strip width (= workgroup size) and rows per workgroup
-  int nstrips, nrowblocks; // ceil(nx / tile_x), ceil(ny / tile_y)
+  int nstrips, nrowblocks; // ceil(nx / tile_x), ceil((y_end - y_begin) / tile_y)
   int nblocks;             // nstrips * nrowblocks
+  int y_begin, y_end;      // rows a launch updates: [y_begin, y_end), normally [0, ny)
 };
 
 // Every model constant the step needs, in FP64; the launcher rounds them to

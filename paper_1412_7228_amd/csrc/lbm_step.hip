@@ -15,7 +15,8 @@ __global__ void __launch_bounds__(BX) k_step(const T* __restrict__ fa, T* __rest
   const int lb = xcd_remap(blockIdx.x, geo.nblocks);
   const int rb = lb / geo.nstrips;
   const int strip = lb - rb * geo.nstrips;
-  step_tile<T, EOS, BX, BIG>(fa, fb, geo, c, strip * BX, rb * geo.tile_y, (rb & 1) != 0, ring);
+  step_tile<T, EOS, BX, BIG>(fa, fb, geo, c, strip * BX, geo.y_begin + rb * geo.tile_y, (rb & 1) != 0,
+                             ring);
 }
 
 template <typename T, int EOS, bool BIG>
@@ -72,7 +73,7 @@ __global__ void __launch_bounds__(BX, sizeof(T) == 4 ? 5 : 1) k_step2(const T* _
   const int lb = xcd_remap(blockIdx.x, geo.nblocks);
   const int rb = lb / geo.nstrips;
   const int strip = lb - rb * geo.nstrips;
-  const int xs = strip * tile2_width<BX>(), y0 = rb * geo.tile_y;
+  const int xs = strip * tile2_width<BX>(), y0 = geo.y_begin + rb * geo.tile_y;
   if (rb & 1)
     step2_tile<T, EOS, BX, BIG, true>(fa, fb, geo, c, xs, y0, lds);
   else

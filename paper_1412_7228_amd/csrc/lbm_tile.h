@@ -95,7 +95,7 @@ __device__ __forceinline__ void gather(const Planes<BIG>& pa, unsigned rr, unsig
 }
 
 // One tile: columns [x0, x0 + tile_x) x rows [y0, y0 + tile_y) (clipped to the
-// lattice), marched upwards (down = false) or downwards.  Neighbouring row
+// lattice and to the launch's rows [y_begin, y_end)), marched upwards (down = false) or downwards.  Neighbouring row
 // blocks march in opposite directions, so the rows they share as halos are
 // gathered by both at about the same time and the second gather hits L2.
 // The gathers of the next row are issued before the current row's collision
@@ -106,7 +106,7 @@ __device__ __forceinline__ void step_tile(const T* __restrict__ fa, T* __restric
                                           bool down, typename V2<T>::t (*ring)[BX + 2]) {
   using T2 = typename V2<T>::t;
   const int nx = geo.nx, ny = geo.ny;
-  const int W = min(BX, nx - x0), H = min(geo.tile_y, ny - y0);
+  const int W = min(BX, nx - x0), H = min(geo.tile_y, geo.y_end - y0);
   const int tx = threadIdx.x;
   const bool active = tx < W;
   const int x = x0 + (active ? tx : W - 1);  // idle lanes gather a valid column

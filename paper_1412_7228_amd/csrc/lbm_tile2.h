@@ -50,7 +50,7 @@ __device__ __forceinline__ void step2_tile(const T* __restrict__ fa, T* __restri
                                            Tile2Lds<T, BX>& L) {
   using T2 = typename V2<T>::t;
   const int nx = geo.nx, ny = geo.ny;
-  const int H = min(geo.tile_y, ny - y0);
+  const int H = min(geo.tile_y, geo.y_end - y0);  // rows past y_end belong to no tile
   const int tx = threadIdx.x;
   const int u = xs - 3 + tx;            // this lane's column before the periodic wrap (>= -3)
   const int x = (u + nx) % nx;          // nx >= 3

@@ -114,6 +114,7 @@ def load_library(path: str | None = None):
         "lbm_init_field": (st, [vp, dp, dp, dp]),
         "lbm_set_distributions": (st, [vp, dp]),
         "lbm_step": (st, [vp, ctypes.c_int64]),
+        "lbm_step_rows": (st, [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
         "lbm_observables": (st, [vp, ctypes.POINTER(Obs)]),
         "lbm_get_field": (st, [vp, ctypes.c_int32, dp]),
         "lbm_save_state": (st, [vp, vp, ctypes.POINTER(ctypes.c_size_t)]),
@@ -264,6 +265,11 @@ class Lattice:
         _check(self.lib.lbm_step(self.h, int(n)))
         return self
 
+    def step_rows(self, n: int, y_begin: int, rows: int):
+        """One launch of n (1 or 2) steps that updates only rows [y_begin, y_begin + rows)."""
+        _check(self.lib.lbm_step_rows(self.h, int(n), int(y_begin), int(rows)))
+        return self
+
     def sync(self):
         _check(self.lib.lbm_sync(self.h))
 
@@ -298,6 +304,20 @@ class Lattice:
     def load_state(self, blob: bytes):
         buf = ctypes.create_string_buffer(blob, len(blob))
         _check(self.lib.lbm_load_state(self.h, buf, len(blob)))
+
+    def state_tensor(self):
+        """The current device state as a torch view [9, ny, pitch] (the library's
+        layout: post-collision values before streaming), in the working precision.
+        Valid until the next step; writes to it change the state."""
+        import torch
+
+        if self._bufs is None:
+            raise RuntimeError("state_tensor needs torch-allocated buffers")
+        ptr = self.info()["f_cur"]
+        buf = next(b for b in self._bufs if b.data_ptr() == ptr)
+        dt = torch.float32 if self.p.precision == PRECISION["fp32"] else torch.float64
+        pitch = (self.nx + 63) // 64 * 64
+        return buf.view(dt)[: 9 * self.ny * pitch].view(9, self.ny, pitch)
 
     def info(self) -> dict:
         step, ptr, pitch = ctypes.c_int64(), ctypes.c_void_p(), ctypes.c_int32()

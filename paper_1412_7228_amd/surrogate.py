@@ -17,7 +17,10 @@ then secant updates).
 
 runs the whole study on the GPU (training set from uneven droplet batches,
 64 targets, every verification a 200 x 200 droplet of radius 40 run for
-20,000 steps) and writes a JSON report.
+20,000 steps) and writes a JSON report.  With ``--train-geometry verify``
+every training droplet is instead a drop of the verification geometry with
+(A, kappa, T/Tc) drawn from the same ranges, so that the measured sigma is a
+function of the network's three inputs alone.
 """
 from __future__ import annotations
 
@@ -74,11 +77,12 @@ class Surrogate:
         return np.stack([ls, Y[:, 1], np.log(Y[:, 2])], axis=1)
 
     def fit(self, X, Y, iters: int = 3000, lr: float = 1e-3, val_frac: float = 0.2,
-            check_every: int = 25, seed: int = 0) -> dict:
+            check_every: int = 25, seed: int = 0, cosine: bool = False) -> dict:
         """X: [n, 3] (A, kappa, T/Tc); Y: [n, 3] (sigma, rho_l, rho_v).  Full-batch Adam on
         a random (1 - val_frac) of the samples; the weights kept are those with the
         lowest sigma error on the held-out rest (checked every `check_every` steps),
-        since ~400 noisy samples cannot pin 33,923 parameters.  Returns the loss
+        since a few hundred samples cannot pin 33,923 parameters.  With ``cosine`` the
+        step size falls from lr to lr / 100 along a half cosine.  Returns the loss
         histories."""
         X = np.asarray(X, float)
         t = self._targets(X, Y)
@@ -95,7 +99,10 @@ class Surrogate:
         done = 0
         while done < iters:
             k = min(check_every, iters - done)
-            train_loss.extend(float(v) for v in self.net.train(k, lr))
+            step = lr
+            if cosine:
+                step = lr * (0.01 + 0.99 * 0.5 * (1.0 + math.cos(math.pi * done / iters)))
+            train_loss.extend(float(v) for v in self.net.train(k, step))
             done += k
             if nv:
                 # the inversion uses only sigma: select on its held-out error
@@ -162,6 +169,30 @@ def training_set(n_batches: int, seed: int, steps: int, side=(64, 512), domains:
     return np.array(X), np.array(Y), bad, sized
 
 
+def training_set_fixed(n_batches: int, seed: int, steps: int, n: int = 200, R: float = 40.0,
+                       domains: int = 256, log=print):
+    """Droplets of one geometry (n x n lattice, initial radius R) with (T/Tc, kappa, A)
+    drawn from the uneven batch's ranges, run in batches of `domains`; returns X, Y
+    of the runs that stayed two-phase and the count that did not."""
+    X, Y, bad = [], [], 0
+    for bi in range(n_batches):
+        draws = inputs.batch_draws(domains, seed + bi, side=(n, n))
+        cases = [dict(n=n, R=R, T_over_Tc=d["T_over_Tc"], A=d["A"], kappa=d["kappa"], seed=d["seed"])
+                 for d in draws]
+        t0 = time.time()
+        res = laplace.run_cases(cases, steps, precision="fp32")
+        for r in res:
+            c = r["case"]
+            if not (r["ok"] and r["sigma"] > 0):
+                bad += 1
+            else:
+                X.append((c["A"], c["kappa"], c["T_over_Tc"]))
+                Y.append((r["sigma"], r["rho_in"], r["rho_out"]))
+        log(f"[surrogate] training batch {bi} ({n}^2, R = {R:g}): "
+            f"{sum(r['ok'] for r in res)}/{len(res)} two-phase, {time.time() - t0:.1f} s")
+    return np.array(X), np.array(Y), bad
+
+
 def verify(specs, steps: int, n: int = 200, R: float = 40.0):
     """One LBM droplet run per (A, kappa, T/Tc) spec; returns sigma (nan if the run failed)."""
     cases = [dict(n=n, R=R, A=a, kappa=k, T_over_Tc=t, seed=i) for i, (a, k, t) in enumerate(specs)]
@@ -175,14 +206,23 @@ def _num(x):
 
 def study(seed: int = 0, n_targets: int = 64, train_batches: int = 4, train_steps: int = 60000,
           verify_steps: int = 20000, side=(64, 512), domains: int = 256, iters: int = 3000,
-          lr: float = 1e-3, log=print) -> dict:
+          lr: float = 1e-3, train_geometry: str = "uneven", cosine: bool = False, log=print) -> dict:
+    """The whole comparison.  ``train_geometry`` "uneven": training droplets as in the
+    uneven batch (`side`, R = u * side, `train_steps` steps); "verify": every training
+    droplet on the verification geometry (200^2, R = 40, `verify_steps` steps)."""
     t_start = time.time()
-    X, Y, bad, sized = training_set(train_batches, seed, train_steps, side=side, domains=domains,
-                                    log=log)
+    if train_geometry == "uneven":
+        X, Y, bad, sized = training_set(train_batches, seed, train_steps, side=side, domains=domains,
+                                        log=log)
+    elif train_geometry == "verify":
+        X, Y, bad = training_set_fixed(train_batches, seed, verify_steps, domains=domains, log=log)
+        sized, train_steps, side = 0, verify_steps, (200, 200)
+    else:
+        raise ValueError(f"unknown training geometry {train_geometry!r}")
     surs, hists = {}, {}
     for name, prior in (("plain", False), ("eq28_prior", True)):
-        surs[name] = Surrogate(seed=seed, prior_eq28=prior)
-        hists[name] = surs[name].fit(X, Y, iters=iters, lr=lr, seed=seed)
+        surs[name] = Surrogate(seed=seed, prior_eq28=prior, max_batch=max(1024, len(X)))
+        hists[name] = surs[name].fit(X, Y, iters=iters, lr=lr, seed=seed, cosine=cosine)
         h = hists[name]
         log(f"[surrogate] {name}: trained on {len(X)} runs: loss {h['train'][0]:.3e} -> "
             f"{h['train'][-1]:.3e}, held-out best {h['best_val']} at step {h['best_iter']}")
@@ -270,8 +310,9 @@ def study(seed: int = 0, n_targets: int = 64, train_batches: int = 4, train_step
 
     rep = dict(
         config=dict(seed=seed, n_targets=n_targets, train_batches=train_batches, domains=domains,
-                    train_steps=train_steps, verify_steps=verify_steps, side=list(side),
-                    verify_lattice=200, verify_radius=40, tolerance=TOLERANCE, iters=iters, lr=lr),
+                    train_geometry=train_geometry, train_steps=train_steps, verify_steps=verify_steps,
+                    side=list(side), verify_lattice=200, verify_radius=40, tolerance=TOLERANCE,
+                    iters=iters, lr=lr, cosine=cosine),
         training=dict(samples=int(len(X)), outside_model_range=int(bad), left_out_for_radius=int(sized),
                       X=X.tolist(), Y=Y.tolist()),
         targets_valid=int(valid.sum()),
@@ -297,10 +338,13 @@ def main():
     ap.add_argument("--verify-steps", type=int, default=20000)
     ap.add_argument("--iters", type=int, default=3000)
     ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--cosine", action="store_true", help="cosine decay of the step size to lr / 100")
+    ap.add_argument("--train-geometry", choices=("uneven", "verify"), default="uneven",
+                    help="training droplets as in the uneven batch, or all on the verification geometry")
     a = ap.parse_args()
     rep = study(seed=a.seed, n_targets=a.targets, train_batches=a.train_batches,
                 train_steps=a.train_steps, verify_steps=a.verify_steps, iters=a.iters, lr=a.lr,
-                log=lambda m: print(m, flush=True))
+                train_geometry=a.train_geometry, cosine=a.cosine, log=lambda m: print(m, flush=True))
     with open(a.out, "w") as f:
         json.dump(rep, f, indent=1)
     print(json.dumps(rep), flush=True)

@@ -96,3 +96,26 @@ def test_training_is_deterministic_and_learns(lbm):
     assert np.array_equal(runs[0][0], runs[1][0]) and np.array_equal(runs[0][1], runs[1][1])
     loss = runs[0][0]
     assert loss[-1] < 0.05 * loss[0]
+
+
+def test_forward_between_training_calls_leaves_training_set(lbm):
+    """Forward and backward calls on other inputs between training calls (a
+    held-out check) do not change what the next training call trains on."""
+    say("mlp training interleaved with forward/backward")
+    g = np.random.default_rng(11)
+    x = g.uniform(-1, 1, (150, 3)).astype(np.float32)
+    t = np.stack([x[:, 0] * x[:, 1], np.cos(x[:, 2]), x[:, 0] - x[:, 2]], 1).astype(np.float32)
+    other = g.uniform(-1, 1, (200, 3)).astype(np.float32)
+    runs = []
+    for interleave in (False, True):
+        net = lbm.MLP(max_batch=256)
+        net.set_params(omlp.init_params(5))
+        net.set_data(x, t)
+        losses = []
+        for _ in range(4):
+            losses.append(net.train(25, 3e-3))
+            if interleave:
+                net.forward(other)
+                net.backward(other, np.ones_like(other))
+        runs.append((np.concatenate(losses), net.params()))
+    assert np.array_equal(runs[0][0], runs[1][0]) and np.array_equal(runs[0][1], runs[1][1])
