@@ -205,8 +205,8 @@ def _num(x):
 
 
 def study(seed: int = 0, n_targets: int = 64, train_batches: int = 4, train_steps: int = 60000,
-          verify_steps: int = 20000, side=(64, 512), domains: int = 256, iters: int = 3000,
-          lr: float = 1e-3, train_geometry: str = "uneven", cosine: bool = False, log=print) -> dict:
+          verify_steps: int = 20000, side=(64, 512), domains: int = 256, iters: int = 20000,
+          lr: float = 1e-3, train_geometry: str = "uneven", cosine: bool = True, log=print) -> dict:
     """The whole comparison.  ``train_geometry`` "uneven": training droplets as in the
     uneven batch (`side`, R = u * side, `train_steps` steps); "verify": every training
     droplet on the verification geometry (200^2, R = 40, `verify_steps` steps)."""
@@ -336,15 +336,17 @@ def main():
     ap.add_argument("--train-steps", type=int, default=60000,
                     help="steps of the training droplets (large drops relax slowly)")
     ap.add_argument("--verify-steps", type=int, default=20000)
-    ap.add_argument("--iters", type=int, default=3000)
+    ap.add_argument("--iters", type=int, default=20000)
     ap.add_argument("--lr", type=float, default=1e-3)
-    ap.add_argument("--cosine", action="store_true", help="cosine decay of the step size to lr / 100")
+    ap.add_argument("--constant-lr", action="store_true",
+                    help="keep the step size constant (default: cosine decay to lr / 100)")
     ap.add_argument("--train-geometry", choices=("uneven", "verify"), default="uneven",
                     help="training droplets as in the uneven batch, or all on the verification geometry")
     a = ap.parse_args()
     rep = study(seed=a.seed, n_targets=a.targets, train_batches=a.train_batches,
                 train_steps=a.train_steps, verify_steps=a.verify_steps, iters=a.iters, lr=a.lr,
-                train_geometry=a.train_geometry, cosine=a.cosine, log=lambda m: print(m, flush=True))
+                train_geometry=a.train_geometry, cosine=not a.constant_lr,
+                log=lambda m: print(m, flush=True))
     with open(a.out, "w") as f:
         json.dump(rep, f, indent=1)
     print(json.dumps(rep), flush=True)
