@@ -207,3 +207,32 @@ def test_two_step_batch_many_domains_equals_single_steps(lbm, tile, precision):
         runs[spp] = [b.f_soa(i) for i in range(len(cfgs))]
     for i in range(len(cfgs)):
         assert np.array_equal(runs[2][i], runs[1][i], equal_nan=True), i
+
+
+@pytest.mark.parametrize("steps_per_pass", [1, 2])
+def test_failing_domain_leaves_the_others_untouched(lbm, steps_per_pass):
+    """A domain that blows up (a drop at 0.95 of the Carnahan-Starling packing limit:
+    the oracle turns every cell non-finite within 10 steps) is reported through its
+    own observables; the other domains of the same launches are bitwise the lattices
+    run alone and report no fault."""
+    say(f"batch with one failing domain, {steps_per_pass} step(s) per launch")
+    cfgs = _cfgs("fp32")
+    bad = 2
+    rho = [_rho0(i, d) for i, d in enumerate(DOMAINS)]
+    nx, ny = DOMAINS[bad]["nx"], DOMAINS[bad]["ny"]
+    rho[bad] = inputs.droplet(nx, ny, 8.0, 0.95, 0.01, W=2.0, noise=1e-3, seed=1)
+    b = lbm.Batch(cfgs)
+    b.set_launch("per_step", 128 if steps_per_pass == 2 else 64, 16, steps_per_pass=steps_per_pass)
+    for i in range(len(DOMAINS)):
+        b.init_field(i, rho[i])
+    b.step(40)
+    obs = b.observables()
+    assert obs[bad]["n_nonfinite"] > 0
+    for i, c in enumerate(cfgs):
+        if i == bad:
+            continue
+        assert obs[i]["n_nonfinite"] == 0 and obs[i]["n_domain"] == 0, i
+        lat = lbm.Lattice(c)
+        lat.init_field(rho[i])
+        lat.step(40)
+        assert np.array_equal(b.f_soa(i), lat.f_soa()), i

@@ -347,3 +347,30 @@ def test_two_steps_per_pass_rejects_narrow_tile(lbm):
         lat.set_launch(64, 16, 2)
     with pytest.raises(lbm.LBMError):
         lat.set_launch(128, 16, 3)
+
+
+@pytest.mark.parametrize("nx,ny,tile,spp", [(130, 37, (128, 16), 2), (300, 45, (256, 16), 2),
+                                            (70, 33, (64, 8), 1), (257, 21, (128, 8), 1)])
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_nan_poisoned_destination_is_fully_overwritten(lbm, precision, nx, ny, tile, spp):
+    """The buffer a launch writes is filled with NaN first (padding included): after
+    the launch no NaN is left in the lattice and the state equals a clean run, so
+    the tiles cover every cell exactly (ragged strips and row blocks included)."""
+    import torch
+
+    say(f"NaN poison {precision} {nx}x{ny} tile {tile} steps/launch {spp}")
+    cfg = dict(nx=nx, ny=ny, eos="cs", T_over_Tc=0.7, A=-0.5, kappa=0.3, precision=precision)
+    rho = inputs.spinodal(nx, ny, 0.183713, noise=1e-2, seed=8)
+    runs = []
+    for poison in (True, False):
+        lat = lbm.Lattice(cfg)
+        lat.set_launch(*tile, spp)
+        lat.init_field(rho)
+        if poison:
+            cur = lat.info()["f_cur"]
+            other = next(t for t in lat._bufs if t.data_ptr() != cur)
+            other.view(torch.float32 if precision == "fp32" else torch.float64).fill_(float("nan"))
+        lat.step(spp)
+        runs.append(lat.state_tensor()[:, :, :nx].clone())
+    assert not torch.isnan(runs[0]).any()
+    assert torch.equal(runs[0], runs[1])
