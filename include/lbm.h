@@ -179,20 +179,31 @@ lbm_status lbm_set_distributions(lbm_ctx* ctx, const double* f);
 /* Enqueues n >= 0 time steps on the context stream and returns. */
 lbm_status lbm_step(lbm_ctx* ctx, int64_t n);
 
+/* Flag of lbm_step_rows: more row ranges of the same steps follow. */
+enum { LBM_ROWS_MORE = 1 };
+
 /* One launch of the same time step (Eqs. 1, 9, 23, 25) that updates only the
  * rows [y_begin, y_begin + rows) of the lattice: n = 1 step, or n = 2 steps
  * when the context runs two steps per pass (lbm_launch.steps_per_pass).  The
  * launch reads the current state's rows within 2n of the range (periodic in
  * y, as lbm_step) and writes the range into the other buffer, which then
- * becomes current; rows outside the range keep whatever that buffer held
- * (the state of an earlier launch).  The paper's lattice is one periodic
- * domain; this entry point is what a y-slab decomposition of it needs: a slab
- * of h rows is a context of h + 4n rows whose first and last 2n rows are
- * ghost rows, updated with (n, 2n, h) and refreshed from the neighbouring
- * slabs' current buffers (lbm_state_info) before the next call.  LBM_EINVAL
- * for n outside {1, 2}, n = 2 with one step per pass, rows < 1 or a range
- * outside [0, ny); LBM_ESTATE before the state is initialised. */
-lbm_status lbm_step_rows(lbm_ctx* ctx, int32_t n, int32_t y_begin, int32_t rows);
+ * becomes current and the step count advances by n; rows outside the range
+ * keep whatever that buffer held (the state of an earlier launch).
+ * flags = LBM_ROWS_MORE: the launch is one range of several for the same n
+ * steps; the source buffer stays current, and the call without the flag that
+ * ends the sequence makes the destination current.  While such a sequence is
+ * open, lbm_step, lbm_set_launch and lbm_save_state return LBM_ESTATE and
+ * another n returns LBM_EINVAL (init, set_distributions and load_state end it).
+ * The paper's lattice is one periodic domain; this entry point is what a
+ * y-slab decomposition of it needs: a slab of h rows is a context of h + 4n
+ * rows whose first and last 2n rows are ghost rows, updated with
+ * (n, 2n, h, 0) and refreshed from the neighbouring slabs' current buffers
+ * (lbm_state_info) before the next call; or, to overlap that refresh, first
+ * the rows that read no ghost row, (n, 4n, h - 4n, LBM_ROWS_MORE), then the
+ * two ranges next to the ghost rows once they have arrived.  LBM_EINVAL for
+ * n outside {1, 2}, n = 2 with one step per pass, rows < 1, a range outside
+ * [0, ny) or unknown flags; LBM_ESTATE before the state is initialised. */
+lbm_status lbm_step_rows(lbm_ctx* ctx, int32_t n, int32_t y_begin, int32_t rows, int32_t flags);
 
 /* Computes the observables in FP64 on the device (deterministic reduction
  * order), synchronises and fills *out.  Returns LBM_ENONFINITE or

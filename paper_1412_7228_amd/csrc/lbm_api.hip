@@ -308,6 +308,7 @@ struct lbm_ctx {
   bool own_stream;
   int64_t step;
   bool initialized;
+  int pending;  // steps of a row-range launch whose destination is not yet current (0: none)
   // FP64 scratch for fields and observables (allocated on first use)
   double* work;      // 4 * nx*ny: rho, U, psi, out
   double* partials;  // obs_partials_count * kNumRed
@@ -564,6 +565,7 @@ void lbm_destroy(lbm_ctx* c) {
 
 lbm_status lbm_set_launch(lbm_ctx* c, const lbm_launch* l) {
   if (!c || !l) return fail(LBM_EINVAL, "NULL argument");
+  if (c->pending) return fail(LBM_ESTATE, "lbm_set_launch while a row-range launch is open");
   // steps_per_pass 0: two, unless the tile asked for is too narrow for them
   const int fuse = l->steps_per_pass != 0 ? l->steps_per_pass : (l->tile_x == 64 ? 1 : 2);
   if (fuse != 1 && fuse != 2) return fail(LBM_EINVAL, "steps_per_pass %d not in {1, 2}", l->steps_per_pass);
@@ -621,6 +623,7 @@ lbm_status lbm_init_field(lbm_ctx* c, const double* rho, const double* ux, const
                                   c->buf[c->cur], c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));  // host arrays may go away after return
   c->step = 0;
+  c->pending = 0;
   c->initialized = true;
   return LBM_OK;
 }
@@ -638,6 +641,7 @@ lbm_status lbm_set_distributions(lbm_ctx* c, const double* f) {
   }
   HIP_TRY(hipStreamSynchronize(c->stream));
   c->step = 0;
+  c->pending = 0;
   c->initialized = true;
   return LBM_OK;
 }
@@ -646,6 +650,7 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
   if (!c) return fail(LBM_EINVAL, "NULL context");
   if (n < 0) return fail(LBM_EINVAL, "negative step count");
   if (!c->initialized) return fail(LBM_ESTATE, "lbm_step before lbm_init_field");
+  if (c->pending) return fail(LBM_ESTATE, "lbm_step while a row-range launch is open");
   int64_t left = n;
   // two steps per launch: the buffer written holds the state after both
   if (c->fuse == 2) {
@@ -664,11 +669,14 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
   return LBM_OK;
 }
 
-lbm_status lbm_step_rows(lbm_ctx* c, int32_t n, int32_t y_begin, int32_t rows) {
+lbm_status lbm_step_rows(lbm_ctx* c, int32_t n, int32_t y_begin, int32_t rows, int32_t flags) {
   if (!c) return fail(LBM_EINVAL, "NULL context");
   if (!c->initialized) return fail(LBM_ESTATE, "lbm_step_rows before lbm_init_field");
+  if (flags & ~LBM_ROWS_MORE) return fail(LBM_EINVAL, "lbm_step_rows: unknown flags 0x%x", flags);
   if (n != 1 && !(n == 2 && c->fuse == 2))
     return fail(LBM_EINVAL, "lbm_step_rows: n = %d; one launch does 1 step, or 2 with two steps per pass", n);
+  if (c->pending && n != c->pending)
+    return fail(LBM_EINVAL, "lbm_step_rows: n = %d while a %d-step launch is open", n, c->pending);
   if (rows < 1 || y_begin < 0 || (int64_t)y_begin + rows > c->p.ny)
     return fail(LBM_EINVAL, "lbm_step_rows: rows [%d, %lld) outside [0, %d)", y_begin,
                 (long long)y_begin + rows, c->p.ny);
@@ -682,6 +690,11 @@ lbm_status lbm_step_rows(lbm_ctx* c, int32_t n, int32_t y_begin, int32_t rows) {
     HIP_TRY(launch_step2(prec, g, c->m, c->buf[c->cur], c->buf[1 - c->cur], c->stream));
   else
     HIP_TRY(launch_step(prec, g, c->m, c->buf[c->cur], c->buf[1 - c->cur], c->stream));
+  if (flags & LBM_ROWS_MORE) {
+    c->pending = n;  // more ranges of the same steps follow: the source stays current
+    return LBM_OK;
+  }
+  c->pending = 0;
   c->cur = 1 - c->cur;
   c->step += n;
   return LBM_OK;
@@ -709,6 +722,7 @@ lbm_status lbm_save_state(lbm_ctx* c, void* buf, size_t* len) {
   if (!buf) { *len = need; return LBM_OK; }
   if (*len < need) return fail(LBM_EINVAL, "state buffer of %zu bytes, need %zu", *len, need);
   if (!c->initialized) return fail(LBM_ESTATE, "save before lbm_init_field");
+  if (c->pending) return fail(LBM_ESTATE, "save while a row-range launch is open");
   StateHeader h{kStateMagic, c->p.nx, c->p.ny, c->g.pitch, c->p.precision, c->step,
                 params_hash(c->p), c->buf_bytes};
   std::memcpy(buf, &h, sizeof h);
@@ -734,6 +748,7 @@ lbm_status lbm_load_state(lbm_ctx* c, const void* buf, size_t len) {
                          hipMemcpyHostToDevice, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   c->step = h.step;
+  c->pending = 0;
   c->initialized = true;
   return LBM_OK;
 }

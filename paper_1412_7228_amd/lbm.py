@@ -114,7 +114,7 @@ def load_library(path: str | None = None):
         "lbm_init_field": (st, [vp, dp, dp, dp]),
         "lbm_set_distributions": (st, [vp, dp]),
         "lbm_step": (st, [vp, ctypes.c_int64]),
-        "lbm_step_rows": (st, [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+        "lbm_step_rows": (st, [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
         "lbm_observables": (st, [vp, ctypes.POINTER(Obs)]),
         "lbm_get_field": (st, [vp, ctypes.c_int32, dp]),
         "lbm_save_state": (st, [vp, vp, ctypes.POINTER(ctypes.c_size_t)]),
@@ -265,9 +265,10 @@ class Lattice:
         _check(self.lib.lbm_step(self.h, int(n)))
         return self
 
-    def step_rows(self, n: int, y_begin: int, rows: int):
-        """One launch of n (1 or 2) steps that updates only rows [y_begin, y_begin + rows)."""
-        _check(self.lib.lbm_step_rows(self.h, int(n), int(y_begin), int(rows)))
+    def step_rows(self, n: int, y_begin: int, rows: int, more: bool = False):
+        """One launch of n (1 or 2) steps that updates only rows [y_begin, y_begin + rows);
+        ``more``: further ranges of the same steps follow (the source stays current)."""
+        _check(self.lib.lbm_step_rows(self.h, int(n), int(y_begin), int(rows), 1 if more else 0))
         return self
 
     def sync(self):

@@ -41,17 +41,20 @@ def _lattice(lbm, cfg, n):
     return lat
 
 
-@pytest.mark.parametrize("precision,n,nx,S,h", [
-    ("fp32", 2, 300, 4, 24),   # several strips, ragged last strip
-    ("fp64", 2, 130, 3, 20),
-    ("fp32", 1, 200, 4, 13),   # one step per launch, ragged row blocks
-    ("fp32", 2, 260, 2, 7),    # slabs thinner than a tile
-    ("fp32", 2, 140, 1, 30),   # one slab: its own neighbour on both sides
+@pytest.mark.parametrize("precision,n,nx,S,h,split", [
+    ("fp32", 2, 300, 4, 24, False),  # several strips, ragged last strip
+    ("fp64", 2, 130, 3, 20, False),
+    ("fp32", 1, 200, 4, 13, False),  # one step per launch, ragged row blocks
+    ("fp32", 2, 260, 2, 7, False),   # slabs thinner than a tile
+    ("fp32", 2, 140, 1, 30, False),  # one slab: its own neighbour on both sides
+    ("fp32", 2, 300, 4, 24, True),   # interior rows first, then the rows next to the ghosts
+    ("fp64", 2, 130, 3, 20, True),
+    ("fp32", 1, 200, 4, 13, True),
 ])
-def test_slabs_with_ghost_rows_equal_periodic_lattice(lbm, precision, n, nx, S, h):
+def test_slabs_with_ghost_rows_equal_periodic_lattice(lbm, precision, n, nx, S, h, split):
     import torch
 
-    say(f"{precision} n={n} nx={nx} slabs={S} x {h} rows")
+    say(f"{precision} n={n} nx={nx} slabs={S} x {h} rows split={split}")
     NY, g = S * h, 2 * n
     rho = inputs.spinodal(nx, NY, 0.183713, noise=1e-2, seed=5)
     lat = _lattice(lbm, _cfg(nx, NY, precision), n)
@@ -65,10 +68,9 @@ def test_slabs_with_ghost_rows_equal_periodic_lattice(lbm, precision, n, nx, S, 
         rows = torch.tensor([(s * h - g + r) % NY for r in range(h + 2 * g)], device=full.device)
         sl.state_tensor().copy_(full.index_select(1, rows))
         slabs.append(sl)
-    for launch in range(5):
-        lat.step(n)
-        for sl in slabs:
-            sl.step_rows(n, g, h)
+
+    def refresh():
+        # ghost rows of every slab's current buffer from its neighbours' interior rows
         cur = [sl.state_tensor() for sl in slabs]
         new = [c.clone() for c in cur]
         for s in range(S):
@@ -76,9 +78,27 @@ def test_slabs_with_ghost_rows_equal_periodic_lattice(lbm, precision, n, nx, S, 
             new[s][:, h + g:] = cur[(s + 1) % S][:, g:2 * g]
         for c, m in zip(cur, new):
             c.copy_(m)
+
+    for launch in range(5):
+        lat.step(n)
+        if split:
+            # the ghost rows have not arrived yet: the rows that read none of them go first
+            for sl in slabs:
+                t = sl.state_tensor()
+                t[:, :g] = float("nan")
+                t[:, h + g:] = float("nan")
+                sl.step_rows(n, 2 * g, h - 2 * g, more=True)
+            refresh()
+            for sl in slabs:
+                sl.step_rows(n, g, g, more=True)
+                sl.step_rows(n, h, g)
+        else:
+            for sl in slabs:
+                sl.step_rows(n, g, h)
+            refresh()
         full = lat.state_tensor()
         for s in range(S):
-            a = cur[s][:, g:g + h, :nx]
+            a = slabs[s].state_tensor()[:, g:g + h, :nx]
             b = full[:, s * h:(s + 1) * h, :nx]
             assert torch.equal(a, b), f"slab {s} differs after launch {launch}"
     for sl in slabs:
@@ -140,3 +160,25 @@ def test_step_rows_rejects_bad_arguments(lbm):
     with pytest.raises(lbm.LBMError):
         one.step_rows(2, 0, 30)  # two steps need two steps per pass
     one.step_rows(1, 0, 30)
+
+
+def test_open_row_range_launch_state_rules(lbm):
+    """While a row-range launch is open (more ranges of the same steps to come), the
+    source buffer stays current, lbm_step and set_launch are refused, another step
+    count is refused, and the closing call makes the destination current."""
+    say("open row-range launch")
+    lat = _lattice(lbm, _cfg(130, 30, "fp32"), 2)
+    lat.init_field(np.full((30, 130), 0.2))
+    before = lat.info()
+    lat.step_rows(2, 0, 10, more=True)
+    assert lat.info() == before  # still the source buffer and the same step
+    with pytest.raises(lbm.LBMError):
+        lat.step(2)
+    with pytest.raises(lbm.LBMError):
+        lat.set_launch(0, 0, 1)
+    with pytest.raises(lbm.LBMError):
+        lat.step_rows(1, 10, 10)
+    lat.step_rows(2, 10, 20)
+    after = lat.info()
+    assert after["step"] == 2 and after["f_cur"] != before["f_cur"]
+    lat.step(2)  # allowed again
