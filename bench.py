@@ -61,6 +61,7 @@ def parse():
     ap.add_argument("--fp64-steps", type=int, default=500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-slab", action="store_true", help="skip the one-GPU slab share measurement")
+    ap.add_argument("--no-e2e", action="store_true", help="skip the end-to-end small workloads")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--tile", type=str, default="", help="tile_x,tile_y of the step kernel")
     ap.add_argument("--copy-mib", type=int, default=1024,
@@ -212,6 +213,44 @@ def slab_share(launches=300, slabs=8, tiles=((0, 0), (256, 16), (256, 8), (128, 
                 exchange_bytes=2 * 9 * g * N * 4, n_nonfinite=ob["n_nonfinite"])
 
 
+def end_to_end():
+    """Wall time of two small workloads from initial field to observables: the 100^2 FP64
+    droplet (CS, 0.8Tc, R = 25, 5000 steps) on the GPU and on the oracle (all host cores),
+    and the 200^2 Laplace sweep (R 20..60, T/Tc 0.6..0.8, kappa 0..0.6 at A = -0.5, plus
+    the A = -0.9 rows at 0.6Tc; 60 drops, 20,000 FP32 steps) as one batch on the GPU."""
+    import torch
+    import oracle
+    from paper_1412_7228_amd import inputs, laplace, lbm
+
+    cfg = dict(nx=100, ny=100, eos="cs", T_over_Tc=0.8, A=-0.5, kappa=0.0, precision="fp64")
+    rv, rl = lbm.coexistence(cfg)
+    rho = inputs.droplet(100, 100, 25.0, rl, rv, W=5.0, noise=1e-3, seed=0)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    lat = lbm.Lattice(cfg)
+    lat.init_field(rho)
+    lat.step(5000)
+    ob_gpu = lat.observables()
+    gpu_s = time.perf_counter() - t
+    lat.close()
+    nthr = int(os.environ.get("OMP_NUM_THREADS") or min(16, os.cpu_count() or 1))
+    t = time.perf_counter()
+    o = oracle.Oracle(cfg, nthreads=nthr)
+    o.init_field(rho)
+    o.run(5000)
+    ob_orc = o.observables()
+    orc_s = time.perf_counter() - t
+    cases = laplace.sweep_cases(extra_A=(-0.9, (0.6,)))
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    res = laplace.run_cases(cases, 20000, precision="fp32")
+    sweep_s = time.perf_counter() - t
+    return dict(droplet_100_fp64_5000=dict(gpu_s=round(gpu_s, 3), oracle_s=round(orc_s, 3), oracle_threads=nthr,
+                                           sigma_gpu=ob_gpu["sigma"], sigma_oracle=ob_orc["sigma"]),
+                laplace_sweep_200_fp32_20000=dict(drops=len(cases), gpu_s=round(sweep_s, 3),
+                                                 two_phase=int(sum(r["ok"] for r in res))))
+
+
 def cpu_baseline(seconds):
     """The FP64 oracle (as it stands) on the full 4096^2 input, all host cores, as many
     whole steps as fit in about `seconds`."""
@@ -228,9 +267,14 @@ def cpu_baseline(seconds):
     t = time.perf_counter()
     o.run(k)
     dt = time.perf_counter() - t
+    o.nthreads = 1
+    t = time.perf_counter()
+    o.run(1)
+    one_thread = N * N / (time.perf_counter() - t) / 1e6
     return dict(value=N * N * k / dt / 1e6, unit="MLUPS", cores=nthr, kind="oracle",
                 sample=f"4096x4096 lattice (the benchmark's input), {k} FP64 steps after 1 untimed, "
-                       f"{dt:.1f} s on {nthr} threads")
+                       f"{dt:.1f} s on {nthr} threads",
+                single_thread_mlups=round(one_thread, 2))
 
 
 def main():
@@ -258,6 +302,11 @@ def main():
         print("[bench] slab share (8 y-slabs)", file=sys.stderr, flush=True)
         slab = slab_share()
         print(f"[bench] slab {slab}", file=sys.stderr, flush=True)
+    e2e = None
+    if not a.no_e2e:
+        print("[bench] end-to-end workloads", file=sys.stderr, flush=True)
+        e2e = end_to_end()
+        print(f"[bench] end-to-end {e2e}", file=sys.stderr, flush=True)
     copy = None
     if a.copy_mib > 0:
         copy = copy_bandwidth(a.copy_mib)
@@ -294,6 +343,7 @@ def main():
             "roofline": r64["roofline"],
         },
         "slab_share": slab,
+        "end_to_end": e2e,
         "cpu_baseline": cpu,
         "copy_ceiling": None if copy is None else {
             "gbs": round(copy["gbs"], 1), "bytes": copy["bytes_per_copy"],
