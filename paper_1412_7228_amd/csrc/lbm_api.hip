@@ -309,6 +309,13 @@ struct lbm_ctx {
   int64_t step;
   bool initialized;
   int pending;  // steps of a row-range launch whose destination is not yet current (0: none)
+  // graphs of runs of two-step launches (captured on cap_stream, launched on stream)
+  hipStream_t cap_stream;
+  struct GraphEntry {
+    hipGraphExec_t exec;
+    int launches, parity, version;
+  } graphs[4];
+  int ngraphs, version;  // version: bumped whenever the launch geometry changes
   // FP64 scratch for fields and observables (allocated on first use)
   double* work;      // 4 * nx*ny: rho, U, psi, out
   double* partials;  // obs_partials_count * kNumRed
@@ -504,6 +511,46 @@ lbm_status read_field(const lbm_params& p, const ModelConsts& m, const Geometry&
   return LBM_OK;
 }
 
+constexpr int kGraphMinLaunches = 8;   // shorter runs are launched one by one
+constexpr int kGraphMaxLaunches = 64;  // launches per captured graph
+
+// The graph of k two-step launches starting from buffer c->cur (cached per k,
+// starting buffer and launch geometry; at most four kept).
+lbm_status step2_graph(lbm_ctx* c, int k, hipGraphExec_t* out) {
+  for (int i = 0; i < c->ngraphs; ++i) {
+    const auto& g = c->graphs[i];
+    if (g.launches == k && g.parity == c->cur && g.version == c->version) {
+      *out = g.exec;
+      return LBM_OK;
+    }
+  }
+  if (!c->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+  hipError_t e = hipSuccess;
+  int cur = c->cur;
+  for (int i = 0; i < k && e == hipSuccess; ++i, cur = 1 - cur)
+    e = launch_step2((lbm_precision)c->p.precision, c->g2, c->m, c->buf[cur], c->buf[1 - cur], c->cap_stream);
+  hipGraph_t graph = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(c->cap_stream, &graph);
+  if (e != hipSuccess || e2 != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return fail(LBM_EDEVICE, "step graph capture: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+  }
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return fail(LBM_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  // keep the newest four: drop the oldest when full
+  if (c->ngraphs == 4) {
+    (void)hipGraphExecDestroy(c->graphs[0].exec);
+    for (int i = 1; i < 4; ++i) c->graphs[i - 1] = c->graphs[i];
+    c->ngraphs = 3;
+  }
+  c->graphs[c->ngraphs++] = {exec, k, c->cur, c->version};
+  *out = exec;
+  return LBM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -560,6 +607,8 @@ void lbm_destroy(lbm_ctx* c) {
   if (c->partials) (void)hipFree(c->partials);
   if (c->red) (void)hipFree(c->red);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
+  for (int i = 0; i < c->ngraphs; ++i) (void)hipGraphExecDestroy(c->graphs[i].exec);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;
 }
 
@@ -593,6 +642,7 @@ lbm_status lbm_set_launch(lbm_ctx* c, const lbm_launch* l) {
     set_geometry2(c, tx, ty);
   }
   c->fuse = fuse;
+  ++c->version;  // cached graphs hold the old shape
   return LBM_OK;
 }
 
@@ -652,8 +702,18 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
   if (!c->initialized) return fail(LBM_ESTATE, "lbm_step before lbm_init_field");
   if (c->pending) return fail(LBM_ESTATE, "lbm_step while a row-range launch is open");
   int64_t left = n;
-  // two steps per launch: the buffer written holds the state after both
+  // two steps per launch: the buffer written holds the state after both; long runs
+  // of launches go as replays of captured graphs (small lattices are launch-bound)
   if (c->fuse == 2) {
+    while (left >= 2 * kGraphMinLaunches) {
+      const int k = (int)std::min<int64_t>(left / 2, kGraphMaxLaunches);
+      hipGraphExec_t exec = nullptr;
+      lbm_status st = step2_graph(c, k, &exec);
+      if (st != LBM_OK) return st;
+      HIP_TRY(hipGraphLaunch(exec, c->stream));
+      if (k & 1) c->cur = 1 - c->cur;
+      left -= 2 * (int64_t)k;
+    }
     for (; left >= 2; left -= 2) {
       HIP_TRY(launch_step2((lbm_precision)c->p.precision, c->g2, c->m, c->buf[c->cur],
                            c->buf[1 - c->cur], c->stream));
