@@ -142,3 +142,20 @@ def test_taylor_green_decay_single_phase(oracle_mod, s_nu):
         errs.append(abs(rate / (2 * nu * k * k) - 1))
     assert errs[-1] < 0.01
     assert errs[0] / errs[1] > 3.0 and errs[1] / errs[2] > 3.0
+
+
+def test_step_overwrites_a_nan_filled_destination(oracle_mod):
+    """One oracle step into a destination filled with NaN leaves no NaN: every
+    population of every cell is written (push streaming reaches each target once)."""
+    o = _drop(oracle_mod, 19, 13, R=4)
+    n = 19 * 13
+    out = np.full(9 * n, np.nan)
+    work = np.full(3 * n, np.nan)
+    nd, nb = oracle_mod.ctypes.c_int64(0), oracle_mod.ctypes.c_int64(0)
+    oracle_mod._load().orc_step(oracle_mod.ctypes.byref(o.p), oracle_mod._ptr(o.f.reshape(-1)),
+                                oracle_mod._ptr(out), oracle_mod._ptr(work),
+                                oracle_mod.ctypes.byref(nd), oracle_mod.ctypes.byref(nb))
+    assert np.isfinite(out).all()
+    ref = _drop(oracle_mod, 19, 13, R=4)
+    ref.run(1)
+    assert np.array_equal(out, ref.f.reshape(-1))
