@@ -41,7 +41,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # vector ALU peak without packed math: 256 CUs x 64 lanes x 2 (FMA) x 2.4 GHz;
-# the same for FP32 and FP64 on MI355X (packed FP32 is not used by this build)
+# the same for FP32 and FP64 on MI355X (the kernels are compiled without packed FP32)
 ALU_PEAK_TFLOPS = {"fp32": 78.6, "fp64": 78.6}
 FLOPS_PER_LU = 260  # FP arithmetic of one cell update in the single-step kernel's ISA
 # HBM bytes per launch of the two-step kernel in the default shape on 4096^2,
@@ -116,13 +116,14 @@ def gpu_measure(precision, steps, warmup, tile):
         lat.set_launch(*tile)
     lat.init_field(inputs.spinodal(N, N, RHO_MEAN, noise=1e-2, seed=0))
     spp = lat.launch[2]
-    if steps % spp:
-        steps += spp - steps % spp  # whole launches only
-    ms = time_steps(lat, steps, warmup)
+    ms = time_steps(lat, steps, warmup)  # exactly `steps` (an odd count ends with one single step)
     ob = lat.observables(check=False)
     lus = float(N * N) * steps
-    launches = steps // spp
-    per_launch_s = ms * 1e-3 / launches
+    if steps % spp == 0:
+        per_launch_s = ms * 1e-3 / (steps // spp)
+    else:
+        # the roofline is the fused kernel's: time whole launches of it on their own
+        per_launch_s = time_steps(lat, max(spp, steps - steps % spp), 0) * 1e-3 / max(1, steps // spp)
     # bytes the launch must move: the state in and out once per launch
     gbs = BYTES_PER_LU[precision] * N * N / per_launch_s / 1e9
     tflops = FLOPS_PER_LU * N * N * spp / per_launch_s / 1e12
@@ -280,7 +281,7 @@ def cpu_baseline(seconds):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported (this build has no "
+        print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported (the library has no "
               "multi-GPU path)", file=sys.stderr)
         sys.exit(2)
     import torch

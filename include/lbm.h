@@ -242,7 +242,7 @@ typedef struct lbm_batch lbm_batch;
 typedef enum {
   LBM_BATCH_PERSISTENT = 0, /* one launch advances all domains by n steps; each domain's
                                tiles meet at a per-domain step barrier (bounded wait).
-                               Switched off in this build: lbm_batch_set_launch
+                               Switched off in this version: lbm_batch_set_launch
                                returns LBM_EINVAL for it */
   LBM_BATCH_PER_STEP = 1    /* one launch per step over all tiles, captured in HIP graphs */
 } lbm_batch_mode;

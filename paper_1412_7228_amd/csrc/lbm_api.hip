@@ -1199,7 +1199,7 @@ lbm_status lbm_batch_set_launch(lbm_batch* b, const lbm_batch_launch* l) {
   if (l->mode != LBM_BATCH_PERSISTENT && l->mode != LBM_BATCH_PER_STEP)
     return fail(LBM_EINVAL, "unknown batch mode %d", l->mode);
   if (l->mode == LBM_BATCH_PERSISTENT && !kPersistentEnabled)
-    return fail(LBM_EINVAL, "persistent batch mode is switched off in this build (its kernel has not "
+    return fail(LBM_EINVAL, "persistent batch mode is switched off in this version of the library (its kernel has not "
                             "passed on a GPU); use LBM_BATCH_PER_STEP");
   // steps_per_pass 0: two, unless the mode or a 64-wide tile asks for one
   const int fuse = l->steps_per_pass ? l->steps_per_pass

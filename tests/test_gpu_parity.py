@@ -32,7 +32,7 @@ def lbm():
         pytest.skip("no HIP device visible")
     from paper_1412_7228_amd import lbm as mod
 
-    mod.load_library()  # must load on a GPU machine: no fallback
+    mod.load_library()  # with a HIP device visible the library must load: no fallback
     return mod
 
 
