@@ -215,10 +215,11 @@ def slab_share(launches=300, slabs=8, tiles=((0, 0), (256, 16), (256, 8), (128, 
 
 
 def end_to_end():
-    """Wall time of two small workloads from initial field to observables: the 100^2 FP64
+    """Wall time of workloads from initial field to results: the 100^2 FP64
     droplet (CS, 0.8Tc, R = 25, 5000 steps) on the GPU and on the oracle (all host cores),
     and the 200^2 Laplace sweep (R 20..60, T/Tc 0.6..0.8, kappa 0..0.6 at A = -0.5, plus
-    the A = -0.9 rows at 0.6Tc; 60 drops, 20,000 FP32 steps) as one batch on the GPU."""
+    the A = -0.9 rows at 0.6Tc; 60 drops, 20,000 FP32 steps) as one batch on the GPU, and
+    the benchmark lattice including its host transfers (the rate with PCIe in it)."""
     import torch
     import oracle
     from paper_1412_7228_amd import inputs, laplace, lbm
@@ -241,6 +242,21 @@ def end_to_end():
     o.run(5000)
     ob_orc = o.observables()
     orc_s = time.perf_counter() - t
+    # the benchmark lattice with its host transfers: initial density in (FP64, 134 MB),
+    # 2000 steps, density field out (FP64)
+    big = dict(WORKLOAD, precision="fp32")
+    rho_big = inputs.spinodal(N, N, RHO_MEAN, noise=1e-2, seed=0)
+    lat = lbm.Lattice(big)
+    lat.init_field(rho_big)
+    lat.step(20)
+    lat.field("rho")  # first transfers warm the paths
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    lat.init_field(rho_big)
+    lat.step(2000)
+    out = lat.field("rho")
+    io_s = time.perf_counter() - t
+    lat.close()
     cases = laplace.sweep_cases(extra_A=(-0.9, (0.6,)))
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -249,7 +265,11 @@ def end_to_end():
     return dict(droplet_100_fp64_5000=dict(gpu_s=round(gpu_s, 3), oracle_s=round(orc_s, 3), oracle_threads=nthr,
                                            sigma_gpu=ob_gpu["sigma"], sigma_oracle=ob_orc["sigma"]),
                 laplace_sweep_200_fp32_20000=dict(drops=len(cases), gpu_s=round(sweep_s, 3),
-                                                 two_phase=int(sum(r["ok"] for r in res))))
+                                                 two_phase=int(sum(r["ok"] for r in res))),
+                lattice_4096_fp32_2000_with_host_io=dict(
+                    s=round(io_s, 4), mlups=round(N * N * 2000 / io_s / 1e6, 1),
+                    note="init_field from host FP64 + 2000 steps + density field back to host",
+                    rho_finite=bool(np.isfinite(out).all())))
 
 
 def cpu_baseline(seconds):
