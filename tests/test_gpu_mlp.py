@@ -119,3 +119,33 @@ def test_forward_between_training_calls_leaves_training_set(lbm):
                 net.backward(other, np.ones_like(other))
         runs.append((np.concatenate(losses), net.params()))
     assert np.array_equal(runs[0][0], runs[1][0]) and np.array_equal(runs[0][1], runs[1][1])
+
+
+def test_surrogate_fit_and_inversion_on_a_smooth_law(lbm):
+    """The surrogate pipeline (standardised targets, full-batch training with held-out
+    selection, inversion for kappa on a dense grid) on a closed-form law of the shape
+    Eq. (28) predicts, sigma = s0(A, T) (1 - kappa): the kappa it returns for a target
+    reproduces the target within 2% of sigma (the tolerance of the tuning study)."""
+    say("surrogate fit + inversion on a closed-form law")
+    from paper_1412_7228_amd import surrogate as sg
+
+    g = np.random.default_rng(4)
+    n = 900
+    A = g.uniform(-0.7, -0.3, n)
+    k = g.uniform(0.0, 0.8, n)
+    T = g.uniform(0.6, 0.85, n)
+
+    def law(A, k, T):
+        s0 = 0.05 * np.exp(-6.0 * (T - 0.6)) * (1.0 - 0.4 * A)
+        return np.stack([s0 * (1.0 - k), 0.3 + 0.1 * A - 0.5 * (T - 0.6), 0.02 + 0.05 * (T - 0.6)], 1)
+
+    X = np.stack([A, k, T], 1)
+    sur = sg.Surrogate(seed=1, max_batch=1024)
+    sur.fit(X, law(A, k, T), iters=4000, lr=1e-3, cosine=True)
+    At = g.uniform(-0.65, -0.35, 20)
+    Tt = g.uniform(0.62, 0.83, 20)
+    kt = g.uniform(0.05, 0.75, 20)
+    target = law(At, kt, Tt)[:, 0]
+    kinv = sur.invert_kappa(At, Tt, target)
+    got = law(At, kinv, Tt)[:, 0]
+    assert np.abs(got / target - 1).max() < 0.02, np.abs(got / target - 1).max()
