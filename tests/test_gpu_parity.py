@@ -404,3 +404,53 @@ def test_graph_replays_equal_launches_one_by_one(lbm, precision):
         b.step(2)
     assert torch.equal(a.state_tensor()[:, :, :nx], b.state_tensor()[:, :, :nx])
     assert a.info()["step"] == b.info()["step"]
+
+
+@pytest.mark.parametrize("precision,mass_tol", [("fp32", 1e-6), ("fp64", 1e-12)])
+def test_benchmark_workload_full_length(lbm, precision, mass_tol):
+    """The benchmark's 4096^2 spinodal workload for its full 10,000 steps in the default
+    launch: every density finite and positive, no U > 0 cell, mass and momentum kept
+    (FP64 to 1e-12, FP32 to 1e-6 relative), and the mixture separated into two phases."""
+    say(f"4096^2 {precision} 10000 steps")
+    n = 4096
+    cfg = dict(nx=n, ny=n, eos="cs", T_over_Tc=0.7, A=-0.5, kappa=0.0, precision=precision)
+    lat = lbm.Lattice(cfg)
+    lat.init_field(inputs.spinodal(n, n, 0.183713, noise=1e-2, seed=0))
+    o0 = lat.observables()
+    lat.step(10000)
+    o1 = lat.observables()
+    assert o1["n_nonfinite"] == 0 and o1["n_domain"] == 0
+    assert abs(o1["mass"] / o0["mass"] - 1) < mass_tol
+    assert abs(o1["mom_x"] - o0["mom_x"]) < 10 * mass_tol * o0["mass"]
+    assert abs(o1["mom_y"] - o0["mom_y"]) < 10 * mass_tol * o0["mass"]
+    assert o1["rho_max"] > 10 * o1["rho_min"] > 0
+    lat.close()
+
+
+def test_gas_collapse_is_flagged(lbm, oracle_mod):
+    """CS at 0.6Tc with A = -0.3 has no vapour branch on the lattice: the gas around a drop
+    collapses and the state turns non-finite within 500 steps, in the oracle and on the
+    GPU alike; the library reports it (LBM_ENONFINITE from lbm_observables, the count in
+    the record) instead of returning a state.  A = -0.5 at the same temperature stays
+    finite in both."""
+    say("gas collapse at 0.6Tc, A = -0.3")
+    e = th.carnahan_starling()
+    _, Tc = th.critical_point(e)
+    rv, rl = th.maxwell(e, 0.6 * Tc)
+    rho = inputs.droplet(64, 64, 16, rl, rv, W=5.0, noise=1e-3, seed=0)
+    for A, collapses in ((-0.3, True), (-0.5, False)):
+        cfg = dict(nx=64, ny=64, eos="cs", T_over_Tc=0.6, A=A, kappa=0.0, precision="fp64")
+        o = oracle_mod.Oracle(cfg, nthreads=4)
+        o.init_field(rho)
+        o.run(500)
+        assert (o.observables()["n_nonfinite"] > 0) == collapses
+        lat = lbm.Lattice(cfg)
+        lat.init_field(rho)
+        lat.step(500)
+        ob = lat.observables(check=False)
+        assert (ob["n_nonfinite"] > 0) == collapses, A
+        if collapses:
+            assert ob["status"] == -4
+            with pytest.raises(lbm.LBMError):
+                lat.observables()
+        lat.close()
