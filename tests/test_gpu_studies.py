@@ -112,3 +112,21 @@ def test_pr_laplace_law_and_kappa_scaling(studies):
     assert r0["two_phase"] == 3 and r9["two_phase"] == 3
     assert r0["spread"] < 0.05
     assert abs(r9["sigma_ratio"] / 0.1 - 1) < 0.06
+
+
+def test_surrogate_needs_fewer_lbm_runs_than_the_methods_without_it(studies):
+    """What the trained network gains: on a small version of the tuning study (one batch
+    of 256 training drops on the verification geometry, 12 targets), inverting the
+    network for kappa and verifying with one LBM run (one correction allowed) reaches
+    every target sigma within 2% in fewer LBM runs per target than the plain kappa
+    sweep (10) and than the secant guided by Eq. (28)."""
+    say("surrogate study, small")
+    from paper_1412_7228_amd import surrogate
+
+    rep = surrogate.study(seed=3, n_targets=12, train_batches=1, domains=256, train_geometry="verify",
+                          iters=6000, log=lambda m: print(m, flush=True))
+    assert rep["targets_valid"] >= 8
+    best = min((rep[k]["with_one_correction"] for k in ("surrogate", "surrogate_eq28_prior")),
+               key=lambda r: r["mean_runs"])
+    assert best["success"] == 1.0
+    assert best["mean_runs"] < rep["secant_eq28"]["mean_runs"] <= rep["plain_sweep"]["mean_runs"]
