@@ -30,24 +30,47 @@ def lbm():
     return mod
 
 
+OBS_KEYS = ("mass", "rho_in", "rho_out", "dp", "R_e", "sigma", "max_u")
+
+
 def test_fp32_laplace_droplets_match_fp64_oracle(lbm, oracle_mod):
+    """Also reports each observable's relative error against the oracle, FP32 and FP64,
+    and the density field's error for the R = 40 drop (printed as JSON lines)."""
+    import json
+
     steps = 20000
     cases = [dict(n=200, R=R, T_over_Tc=0.8, A=-0.5, kappa=0.3, seed=i) for i, R in enumerate((20, 40, 60))]
-    say(f"laplace fp32 batch, 3 droplets x {steps} steps")
+    say(f"laplace fp32 + fp64 batches, 3 droplets x {steps} steps")
     gpu = laplace.run_cases(cases, steps, precision="fp32")
-    assert all(r["ok"] for r in gpu)
+    gpu64 = laplace.run_cases(cases, steps, precision="fp64")
+    assert all(r["ok"] for r in gpu) and all(r["ok"] for r in gpu64)
     nthr = int(os.environ.get("OMP_NUM_THREADS") or min(16, os.cpu_count() or 1))
     orc = []
-    for c, g in zip(cases, gpu):
+    for c, g, g64 in zip(cases, gpu, gpu64):
         say(f"oracle R={c['R']}")
         cfg = laplace.case_config(c, "fp64")
+        rho0 = laplace.initial_density(c, cfg)
         o = oracle_mod.Oracle(cfg, nthreads=nthr)
-        o.init_field(laplace.initial_density(c, cfg))
+        o.init_field(rho0)
         o.run(steps)
         ob = o.observables()
         orc.append(ob)
+        err = {p: {k: abs(r[k] / ob[k] - 1) for k in OBS_KEYS} for p, r in (("fp32", g), ("fp64", g64))}
+        if c["R"] == 40:
+            ref = o.fields()["rho"]
+            for p in ("fp32", "fp64"):
+                lat = lbm.Lattice(dict(cfg, precision=p))
+                lat.init_field(rho0)
+                lat.step(steps)
+                d = lat.field("rho") - ref
+                err[p]["rho_field_linf"] = float(np.abs(d).max() / np.abs(ref).max())
+                err[p]["rho_field_l2"] = float(np.sqrt((d * d).sum() / (ref * ref).sum()))
+                lat.close()
+        print("[observable-errors] " + json.dumps(dict(R=c["R"], steps=steps, **err)), flush=True)
         for k in ("rho_in", "rho_out", "sigma"):
-            assert abs(g[k] / ob[k] - 1) < 5e-3, (c["R"], k, g[k], ob[k])
+            assert err["fp32"][k] < 5e-3, (c["R"], k, g[k], ob[k])
+        for k in OBS_KEYS:
+            assert err["fp64"][k] < 1e-9, (c["R"], k, g64[k], ob[k])
     # the Laplace fit over radii (finite-size effects of a drop of radius 60 in a
     # 200^2 periodic box are shared by both sides)
     s_gpu, _ = laplace.laplace_sigma(gpu)
