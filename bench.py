@@ -131,6 +131,13 @@ def gpu_measure(precision, steps, warmup, tile):
     traffic = MEASURED_TRAFFIC.get((precision, tx, ty)) if spp == 2 else None
     roof = dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(gbs / HBM_PEAK_GBS, 4), traffic=traffic)
+    # bytes per lattice update, counted explicitly: the method's 72 B (FP32) / 144 B (FP64)
+    # per update, the fused launch's minimum (the state in and out once for spp updates)
+    # and what the counters measured
+    roof["bytes_per_update"] = dict(method=BYTES_PER_LU[precision],
+                                    launch_minimum=round(BYTES_PER_LU[precision] / spp, 1),
+                                    measured=round(traffic / (spp * N * N), 1) if traffic else None,
+                                    updates_per_launch=spp * N * N)
     if traffic:
         roof["traffic_gbs"] = round(traffic / per_launch_s / 1e9, 1)
     if spp == 2:
