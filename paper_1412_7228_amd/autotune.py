@@ -8,13 +8,14 @@ for a batch the sorted domain sizes), in ``$LBM_TUNE_CACHE`` or
 """
 from __future__ import annotations
 
+import hashlib
 import json
 import os
 
 # (tile_x, tile_y, steps_per_pass)
 LATTICE_CANDIDATES = [(256, 16, 1), (256, 64, 1), (128, 32, 1), (64, 32, 1),
-                      (256, 12, 2), (256, 16, 2), (256, 20, 2), (256, 24, 2), (256, 32, 2),
-                      (128, 16, 2), (128, 32, 2), (128, 64, 2)]
+                      (256, 8, 2), (256, 12, 2), (256, 16, 2), (256, 20, 2), (256, 24, 2), (256, 32, 2),
+                      (128, 8, 2), (128, 16, 2), (128, 32, 2), (128, 64, 2)]
 # (mode, tile_x, tile_y, steps_per_pass); the persistent mode is switched off in
 # the library for now
 BATCH_CANDIDATES = [("per_step", 64, 16, 1), ("per_step", 64, 32, 1), ("per_step", 128, 16, 1),
@@ -64,12 +65,24 @@ def _time(stream, fn, steps: int) -> float:
     return e0.elapsed_time(e1) / steps
 
 
+def lattice_key(device: str, nx: int, ny: int, cfg: dict) -> str:
+    return f"lattice|{device}|{nx}x{ny}|{cfg['precision']}|{cfg['eos']}"
+
+
+def batch_key(device: str, shapes, cfg: dict) -> str:
+    """Key of a batch: the device, the number of domains, a digest of the sorted domain
+    sizes (a digest, not hash(): str hashes change from one Python process to the next),
+    the precision and the EOS."""
+    sizes = sorted(f"{ny}x{nx}" for ny, nx in shapes)
+    sig = hashlib.sha1(",".join(sizes).encode()).hexdigest()[:12]
+    return f"batch|{device}|{len(sizes)}|{sig}|{cfg['precision']}|{cfg['eos']}"
+
+
 def tune_lattice(lat, steps: int = 40, candidates=None, use_cache: bool = True) -> dict:
     """Pick the fastest (tile_x, tile_y, steps_per_pass) for a Lattice (its state
     advances by the timing steps).  Returns {"tile": [tx, ty, spp], "ms": ...,
     "table": [...]} with ms per step."""
-    c = lat.cfg
-    key = f"lattice|{_device()}|{lat.nx}x{lat.ny}|{c['precision']}|{c['eos']}"
+    key = lattice_key(_device(), lat.nx, lat.ny, lat.cfg)
     cache = _load() if use_cache else {}
     if key in cache and len(cache[key]["tile"]) == 3:
         lat.set_launch(*cache[key]["tile"])
@@ -92,10 +105,7 @@ def tune_lattice(lat, steps: int = 40, candidates=None, use_cache: bool = True) 
 def tune_batch(batch, steps: int = 20, candidates=None, use_cache: bool = True) -> dict:
     """Pick the fastest (mode, tile_x, tile_y, steps_per_pass) for a Batch (its
     state advances).  ms is per step."""
-    sizes = sorted(f"{ny}x{nx}" for ny, nx in batch.shapes)
-    sig = str(abs(hash(",".join(sizes))) % (10 ** 12))
-    c = batch.cfgs[0]
-    key = f"batch|{_device()}|{len(sizes)}|{sig}|{c['precision']}|{c['eos']}"
+    key = batch_key(_device(), batch.shapes, batch.cfgs[0])
     cache = _load() if use_cache else {}
     if key in cache and len(cache[key]["launch"]) == 4:
         mode, tx, ty, spp = cache[key]["launch"]
