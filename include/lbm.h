@@ -214,17 +214,24 @@ lbm_status lbm_step_rows(lbm_ctx* ctx, int32_t n, int32_t y_begin, int32_t rows,
  * LBM_EDOMAIN (after filling *out) if the state holds such cells. */
 lbm_status lbm_observables(lbm_ctx* ctx, lbm_obs* out);
 
-/* Copies one field (lbm_field) of the current state to host out[y][x] in FP64. */
+/* Copies one field (lbm_field) of the current state to host out[y][x] in FP64
+ * (nx*ny doubles, owned by the caller); synchronises the context stream.
+ * LBM_EINVAL for an unknown field or NULL, LBM_ESTATE before the state is
+ * initialised. */
 lbm_status lbm_get_field(lbm_ctx* ctx, int32_t which, double* out);
 
 /* Checkpoint: *len receives the byte size when buf is NULL; otherwise buf
- * (of *len bytes) receives a header (sizes, precision, step, parameter hash)
- * followed by the raw distribution buffer.  lbm_load_state restores such a
- * blob into a context with the same parameters (LBM_EINVAL otherwise). */
+ * (of *len bytes, host memory owned by the caller) receives a header (sizes,
+ * precision, step, parameter hash) followed by the raw distribution buffer
+ * (LBM_EINVAL if *len is too small, LBM_ESTATE before the state is
+ * initialised or while a row-range launch is open).  lbm_load_state restores
+ * such a blob into a context with the same parameters (LBM_EINVAL otherwise);
+ * both synchronise the context stream.  A saved and reloaded run continues
+ * bitwise as if uninterrupted. */
 lbm_status lbm_save_state(lbm_ctx* ctx, void* buf, size_t* len);
 lbm_status lbm_load_state(lbm_ctx* ctx, const void* buf, size_t len);
 
-/* Waits for the context stream. */
+/* Waits for the context stream (LBM_EDEVICE if a HIP call failed). */
 lbm_status lbm_sync(lbm_ctx* ctx);
 
 /* Current step count and the device pointer of the buffer that holds the
