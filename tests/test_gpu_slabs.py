@@ -182,3 +182,42 @@ def test_open_row_range_launch_state_rules(lbm):
     after = lat.info()
     assert after["step"] == 2 and after["f_cur"] != before["f_cur"]
     lat.step(2)  # allowed again
+
+
+@pytest.mark.parametrize("precision,nx,S,h", [("fp32", 300, 4, 24), ("fp64", 130, 2, 20)])
+def test_deep_ghost_zone_two_launches_per_exchange(lbm, precision, nx, S, h):
+    """Slabs with 8 ghost rows per side exchange once per two launches of two steps:
+    the first launch also updates the inner 4 ghost rows on each side (rows [4, h + 12)),
+    the second only the slab (rows [8, h + 8)); the slabs then hold the periodic
+    lattice's rows bit for bit."""
+    import torch
+
+    say(f"deep ghost zone {precision} {S} slabs x {h} rows")
+    NY, g = S * h, 8
+    rho = inputs.spinodal(nx, NY, 0.183713, noise=1e-2, seed=11)
+    lat = _lattice(lbm, _cfg(nx, NY, precision), 2)
+    lat.init_field(rho)
+    full = lat.state_tensor()
+    slabs = []
+    for s in range(S):
+        sl = _lattice(lbm, _cfg(nx, h + 2 * g, precision), 2)
+        sl.init_field(np.full((h + 2 * g, nx), 0.2))
+        rows = torch.tensor([(s * h - g + r) % NY for r in range(h + 2 * g)], device=full.device)
+        sl.state_tensor().copy_(full.index_select(1, rows))
+        slabs.append(sl)
+    for exchange in range(3):
+        lat.step(4)
+        for sl in slabs:
+            sl.step_rows(2, 4, h + 8)
+            sl.step_rows(2, 8, h)
+        cur = [sl.state_tensor() for sl in slabs]
+        new = [c.clone() for c in cur]
+        for s in range(S):
+            new[s][:, :g] = cur[(s - 1) % S][:, h:h + g]
+            new[s][:, h + g:] = cur[(s + 1) % S][:, g:2 * g]
+        for c, m in zip(cur, new):
+            c.copy_(m)
+        full = lat.state_tensor()
+        for s in range(S):
+            assert torch.equal(slabs[s].state_tensor()[:, g:g + h, :nx], full[:, s * h:(s + 1) * h, :nx]), \
+                (s, exchange)
