@@ -256,7 +256,7 @@ typedef enum {
 
 typedef struct {
   int32_t mode;             /* lbm_batch_mode                                         */
-  int32_t tile_x, tile_y;   /* tile of every domain; 0 = default (128 x 16 with two
+  int32_t tile_x, tile_y;   /* tile of every domain; 0 = default (256 x 16 with two
                                steps per launch, 64 x 32 with one)                   */
   int64_t spin_limit;       /* persistent mode: polls before a barrier wait gives up;
                                0 = default (2^20, about a second)                      */
@@ -279,7 +279,7 @@ typedef struct {
  * null stream as plain launches.
  * LBM_EINVAL if a domain's parameters are invalid or the EOS kinds or
  * precisions differ. Default launch: LBM_BATCH_PER_STEP with two steps per
- * launch, 128 x 16 tiles. */
+ * launch, 256 x 16 tiles. */
 lbm_status lbm_batch_create(const lbm_params* params, int32_t n, void* hip_stream, lbm_batch** out);
 void lbm_batch_destroy(lbm_batch* b);
 

@@ -861,7 +861,7 @@ struct lbm_batch {
   size_t arena_bytes = 0;
   hipStream_t stream = nullptr;
   int mode = LBM_BATCH_PER_STEP;
-  int tile_x = 128, tile_y = 16;
+  int tile_x = 256, tile_y = 16;
   int fuse = 2;                 // per-step mode: steps per launch (1 or 2)
   void* d_tiles2 = nullptr;     // two-step tile list (fuse == 2)
   int ntile2_total = 0;
@@ -1207,7 +1207,7 @@ lbm_status lbm_batch_set_launch(lbm_batch* b, const lbm_batch_launch* l) {
   if (fuse != 1 && fuse != 2) return fail(LBM_EINVAL, "steps_per_pass %d not in {1, 2}", fuse);
   if (fuse == 2 && l->mode != LBM_BATCH_PER_STEP)
     return fail(LBM_EINVAL, "two steps per launch needs the per-step mode");
-  const int tx = l->tile_x ? l->tile_x : (fuse == 2 ? 128 : 64), ty = l->tile_y ? l->tile_y : (fuse == 2 ? 16 : 32);
+  const int tx = l->tile_x ? l->tile_x : (fuse == 2 ? 256 : 64), ty = l->tile_y ? l->tile_y : (fuse == 2 ? 16 : 32);
   if (tx != 64 && tx != 128 && tx != 256) return fail(LBM_EINVAL, "tile_x %d not in {64,128,256}", tx);
   if (fuse == 2 && tx == 64) return fail(LBM_EINVAL, "tile_x 64 too narrow for two steps per launch");
   if (ty < 1) return fail(LBM_EINVAL, "tile_y %d < 1", ty);
