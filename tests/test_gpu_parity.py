@@ -454,3 +454,24 @@ def test_gas_collapse_is_flagged(lbm, oracle_mod):
             with pytest.raises(lbm.LBMError):
                 lat.observables()
         lat.close()
+
+
+def test_graph_replays_on_a_caller_stream(lbm):
+    """A context on a stream of the caller's (not the null stream) replays its graphs
+    on that stream: the state equals that of a context on the null stream."""
+    import torch
+
+    say("graph replays on a caller stream")
+    nx, ny = 140, 60
+    cfg = dict(nx=nx, ny=ny, eos="cs", T_over_Tc=0.7, A=-0.5, kappa=0.3, precision="fp32")
+    rho = inputs.spinodal(nx, ny, 0.183713, noise=1e-2, seed=10)
+    side = torch.cuda.Stream()
+    a = lbm.Lattice(cfg, stream=side)
+    b = lbm.Lattice(cfg)
+    torch.cuda.synchronize()
+    a.init_field(rho)
+    b.init_field(rho)
+    for steps in (300, 34, 300):
+        a.step(steps)
+        b.step(steps)
+        assert np.array_equal(a.f_soa(), b.f_soa()), steps
