@@ -142,6 +142,7 @@ def gpu_measure(precision, steps, warmup, tile):
         roof["traffic_gbs"] = round(traffic / per_launch_s / 1e9, 1)
     if spp == 2:
         roof.update(unfused_equivalent_gbs=round(gbs * 2, 1),
+                    frac_at_method_bytes=round(gbs * 2 / HBM_PEAK_GBS, 4),
                     alu=dict(achieved=round(tflops, 2), peak=ALU_PEAK_TFLOPS[precision], unit="TFLOP/s",
                              frac=round(tflops / ALU_PEAK_TFLOPS[precision], 4)))
     res = dict(ms_per_step=ms / steps, mlups=lus / (ms * 1e-3) / 1e6, steps=steps,
