@@ -52,7 +52,8 @@ def test_defaults_and_strerror(lib):
 
 @pytest.mark.parametrize("bad", [dict(nx=2), dict(ny=0), dict(s_nu=2.0), dict(s_e=0.0),
                                  dict(G=0.5), dict(precision_code=7), dict(eos_code=9),
-                                 dict(K=-1.0), dict(T_over_Tc=0.0)])
+                                 dict(K=-1.0), dict(T_over_Tc=0.0),
+                                 dict(nx=65536, ny=65536)])  # one FP64 plane of 32 GiB
 def test_invalid_parameters_are_rejected_before_device_use(lib, bad):
     cfg = dict(nx=16, ny=16)
     cfg.update({k: v for k, v in bad.items() if not k.endswith("_code")})
@@ -119,3 +120,15 @@ def test_caller_buffers_misaligned_or_short_are_rejected(lib, offset, nbytes):
                             need if nbytes is None else nbytes, ctypes.byref(h))
     assert rc == -1 and not h.value
     assert str(need).encode() in lib.lbm_last_error()
+
+
+def test_largest_plane_is_accepted_and_one_more_row_is_not(lib):
+    """One distribution plane must stay below 4 GiB (32-bit offsets inside a plane): an
+    FP32 32768 x 32767 lattice (plane 4,294,836,224 bytes) is valid, 32768 x 32768 is not."""
+    ok = lbm.make_params(dict(nx=32768, ny=32767, precision="fp32"))
+    assert lib.lbm_buffer_bytes(ctypes.byref(ok)) == 9 * 32767 * 32768 * 4
+    bad = lbm.make_params(dict(nx=32768, ny=32768, precision="fp32"))
+    assert lib.lbm_buffer_bytes(ctypes.byref(bad)) == 0
+    h = ctypes.c_void_p()
+    assert lib.lbm_create(ctypes.byref(bad), None, ctypes.byref(h)) == -1
+    assert b"4 GiB" in lib.lbm_last_error()

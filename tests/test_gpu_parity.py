@@ -5,6 +5,7 @@ after 1000 steps of the 100 x 100 droplet; FP32 density within 1e-5.  Launch
 shapes, ragged sizes, every EOS, the U > 0 clamp and the full 4096^2 lattice in
 the benchmark's launch shape are covered.
 """
+import ctypes
 import os
 import sys
 
@@ -475,3 +476,27 @@ def test_graph_replays_on_a_caller_stream(lbm):
         a.step(steps)
         b.step(steps)
         assert np.array_equal(a.f_soa(), b.f_soa()), steps
+
+
+def test_buffer_above_4gib_equals_its_periodic_tile(lbm):
+    """A lattice whose distribution buffer passes 4 GiB (12000 x 10200 FP32: 4.4 GB) runs
+    the kernel variant with one buffer resource per plane.  Its initial density repeats a
+    120 x 102 tile 100 x 100 times; the update is local and translation-invariant, so
+    after two launches every tile must equal the 120 x 102 lattice run alone, bit for bit."""
+    say("12000 x 10200 fp32 (buffer > 4 GiB) vs its 120 x 102 tile")
+    tx, ty, k = 120, 102, 100
+    cfg = dict(eos="cs", T_over_Tc=0.7, A=-0.5, kappa=0.3, precision="fp32")
+    small_rho = inputs.spinodal(tx, ty, 0.183713, noise=1e-2, seed=12)
+    small = lbm.Lattice(dict(cfg, nx=tx, ny=ty))
+    small.init_field(small_rho)
+    small.step(4)
+    ref = small.field("rho")
+    small.close()
+    big = lbm.Lattice(dict(cfg, nx=tx * k, ny=ty * k))
+    assert big.lib.lbm_buffer_bytes(ctypes.byref(big.p)) > (1 << 32)
+    big.init_field(np.tile(small_rho, (k, k)))
+    big.step(4)
+    rho = big.field("rho")
+    big.close()
+    tiles = rho.reshape(k, ty, k, tx)
+    assert np.array_equal(tiles, np.broadcast_to(ref[None, :, None, :], tiles.shape))
