@@ -500,3 +500,23 @@ def test_buffer_above_4gib_equals_its_periodic_tile(lbm):
     big.close()
     tiles = rho.reshape(k, ty, k, tx)
     assert np.array_equal(tiles, np.broadcast_to(ref[None, :, None, :], tiles.shape))
+
+
+def test_zero_steps_change_nothing_and_negative_counts_are_refused(lbm):
+    say("zero and negative step counts")
+    cfg = dict(nx=40, ny=30, eos="cs", T_over_Tc=0.8, A=-0.5, kappa=0.0, precision="fp32")
+    lat = lbm.Lattice(cfg)
+    lat.init_field(inputs.spinodal(40, 30, 0.183713, noise=1e-2, seed=13))
+    f0 = lat.f_soa()
+    lat.step(0)
+    assert np.array_equal(lat.f_soa(), f0) and lat.info()["step"] == 0
+    with pytest.raises(lbm.LBMError):
+        lat.step(-1)
+    b = lbm.Batch([cfg, dict(cfg, nx=20, ny=20)])
+    b.init_field(0, inputs.spinodal(40, 30, 0.183713, noise=1e-2, seed=13))
+    b.init_field(1, inputs.spinodal(20, 20, 0.183713, noise=1e-2, seed=14))
+    g0 = b.f_soa(0)
+    b.step(0)
+    assert np.array_equal(b.f_soa(0), g0)
+    with pytest.raises(lbm.LBMError):
+        b.step(-3)
