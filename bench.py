@@ -47,6 +47,8 @@ FLOPS_PER_LU = 260  # FP arithmetic of one cell update in the single-step kernel
 # HBM bytes per launch of the two-step kernel in the default shape on 4096^2,
 # from rocprofv3 FETCH_SIZE + WRITE_SIZE (scaled by the copy calibration)
 MEASURED_TRAFFIC = {("fp32", 256, 16): (780.4e6 + 618.3e6), ("fp64", 256, 24): (1500.4e6 + 1218.4e6)}
+# VALU issue utilisation of the same launches (SQ_INSTS_VALU against 256 CUs x GRBM_GUI_ACTIVE / 8)
+MEASURED_VALU_ISSUE = {("fp32", 256, 16): 0.801, ("fp64", 256, 24): 0.474}
 N = 4096
 RHO_MEAN = 0.183713  # (rho_v + rho_l)/2 of CS at 0.7Tc: (0.00929415 + 0.35813094)/2
 WORKLOAD = dict(nx=N, ny=N, eos="cs", T_over_Tc=0.7, A=-0.5, kappa=0.0)
@@ -144,7 +146,8 @@ def gpu_measure(precision, steps, warmup, tile):
         roof.update(unfused_equivalent_gbs=round(gbs * 2, 1),
                     frac_at_method_bytes=round(gbs * 2 / HBM_PEAK_GBS, 4),
                     alu=dict(achieved=round(tflops, 2), peak=ALU_PEAK_TFLOPS[precision], unit="TFLOP/s",
-                             frac=round(tflops / ALU_PEAK_TFLOPS[precision], 4)))
+                             frac=round(tflops / ALU_PEAK_TFLOPS[precision], 4),
+                             valu_issue_measured=MEASURED_VALU_ISSUE.get((precision, tx, ty))))
     res = dict(ms_per_step=ms / steps, mlups=lus / (ms * 1e-3) / 1e6, steps=steps,
                launch_ms=per_launch_s * 1e3, roofline=roof, tile=list(lat.launch), mass=ob["mass"],
                n_nonfinite=ob["n_nonfinite"])
