@@ -368,19 +368,36 @@ void default_launch(const lbm_params& p, int* tx, int* ty) {
 }
 
 // Default shape of the two-step launch: 256-lane strips (250 stored columns)
-// where the lattice is that wide, else 128; 16 rows (FP32) or 24 rows (FP64)
-// per workgroup, fewer while that leaves under 4 workgroups per CU.  (On the
-// 4096^2 lattice 14 to 28 rows are within 1.5% of each other in FP32, 16 to 32
-// in FP64; 8 rows lose 12%, 64 rows 15% from the tail of the grid.)
+// with 16 rows (FP32) or 24 rows (FP64) per workgroup, fewer (down to 8) while
+// that leaves under 4 workgroups per CU.  A lattice too small to give 256-lane
+// strips 8 workgroups per CU even then (a slab of a larger lattice, 2048^2 and
+// below) takes 128-lane strips, rows down to 8 for 8 workgroups per CU: more,
+// smaller workgroups finish the grid sooner there (measured, alternating the
+// two shapes: 4096 x 520, 128 x 8 is 3% faster than 256 x 8; 2048^2 and
+// 4096 x 1024, 128 x 16 is 1.5% faster than 256 x 16; 1024^2, 128 x 8 is 6%
+// faster).  On 4096^2 the 256-lane shapes of 14 to 28 rows are within 1.5% of
+// each other in FP32, 16 to 32 in FP64.
 void default_launch2(const lbm_params& p, int* tx, int* ty) {
-  *tx = p.nx >= 250 ? 256 : 128;
   int cus = 0, dev = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
     cus = 256;
-  const long long strips = (p.nx + *tx - kStep2Halo - 1) / (*tx - kStep2Halo);
-  int rows = p.precision == LBM_FP32 ? 16 : 24;
-  while (rows > 8 && strips * ((p.ny + rows - 1) / rows) < 4ll * cus) rows -= 4;
+  const int start = p.precision == LBM_FP32 ? 16 : 24;
+  auto blocks = [&](int w, int rows) {
+    return (long long)((p.nx + w - kStep2Halo - 1) / (w - kStep2Halo)) * ((p.ny + rows - 1) / rows);
+  };
+  auto rows_for = [&](int w, long long target) {
+    int rows = start;
+    while (rows > 8 && blocks(w, rows) < target) rows -= 4;
+    return rows;
+  };
+  int w = 128, rows = 0;
+  if (p.nx >= 250) {
+    rows = rows_for(256, 4ll * cus);
+    if (blocks(256, rows) >= 8ll * cus) w = 256;
+  }
+  if (w == 128) rows = rows_for(128, p.nx >= 250 ? 8ll * cus : 4ll * cus);
+  *tx = w;
   *ty = std::min(rows, p.ny);
 }
 

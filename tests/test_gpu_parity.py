@@ -520,3 +520,18 @@ def test_zero_steps_change_nothing_and_negative_counts_are_refused(lbm):
     assert np.array_equal(b.f_soa(0), g0)
     with pytest.raises(lbm.LBMError):
         b.step(-3)
+
+
+@pytest.mark.parametrize("nx,ny,precision,expect", [
+    (4096, 4096, "fp32", (256, 16, 2)), (4096, 4096, "fp64", (256, 24, 2)),
+    (4096, 520, "fp32", (128, 8, 2)), (2048, 2048, "fp32", (128, 16, 2)), (200, 200, "fp32", (128, 8, 2))])
+def test_default_launch_shape(lbm, nx, ny, precision, expect):
+    """The default two-step launch on a 256-CU device: 256-lane strips where they give 8
+    or more workgroups per CU, else 128-lane strips with rows down to 8."""
+    import torch
+
+    if torch.cuda.get_device_properties(0).multi_processor_count != 256:
+        pytest.skip("the expected shapes are those of a 256-CU device")
+    lat = lbm.Lattice(dict(nx=nx, ny=ny, eos="cs", T_over_Tc=0.7, precision=precision))
+    assert tuple(lat.launch) == expect
+    lat.close()
