@@ -327,7 +327,7 @@ def main():
     r64 = None
     if a.fp64_steps > 0:
         print(f"[bench] fp64 {N}x{N}: timed {a.fp64_steps}", file=sys.stderr, flush=True)
-        r64 = gpu_measure("fp64", a.fp64_steps, max(10, a.warmup // 4), tile)
+        r64 = gpu_measure("fp64", a.fp64_steps, a.warmup, tile)
         print(f"[bench] fp64 {r64}", file=sys.stderr, flush=True)
     slab = None
     if not a.no_slab:

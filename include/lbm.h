@@ -177,10 +177,10 @@ lbm_status lbm_init_field(lbm_ctx* ctx, const double* rho, const double* ux, con
 lbm_status lbm_set_distributions(lbm_ctx* ctx, const double* f);
 
 /* Enqueues n >= 0 time steps on the context stream and returns.  With two
- * steps per pass, runs of 8 or more two-step launches are replayed from HIP
- * graphs of up to 64 launches, captured on a stream of the context's own
- * (kernels only) and cached per length and starting buffer, four at most;
- * the states are bitwise those of the launches issued one by one. */
+ * steps per pass, each run of 64 two-step launches is a replay of a HIP graph
+ * captured on a stream of the context's own (kernels only; cached per starting
+ * buffer and launch shape) and the remaining launches go one by one; the
+ * states are bitwise those of the launches issued one by one. */
 lbm_status lbm_step(lbm_ctx* ctx, int64_t n);
 
 /* Flag of lbm_step_rows: more row ranges of the same steps follow. */

@@ -528,8 +528,10 @@ lbm_status read_field(const lbm_params& p, const ModelConsts& m, const Geometry&
   return LBM_OK;
 }
 
-constexpr int kGraphMinLaunches = 8;   // shorter runs are launched one by one
-constexpr int kGraphMaxLaunches = 64;  // launches per captured graph
+// Runs of two-step launches go as replays of one captured graph of this many
+// launches; the rest of a call (fewer launches) is launched one by one, so a
+// caller who repeats a step count never captures inside its loop.
+constexpr int kGraphLaunches = 64;
 
 // The graph of k two-step launches starting from buffer c->cur (cached per k,
 // starting buffer and launch geometry; at most four kept).
@@ -719,11 +721,11 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
   if (!c->initialized) return fail(LBM_ESTATE, "lbm_step before lbm_init_field");
   if (c->pending) return fail(LBM_ESTATE, "lbm_step while a row-range launch is open");
   int64_t left = n;
-  // two steps per launch: the buffer written holds the state after both; long runs
-  // of launches go as replays of captured graphs (small lattices are launch-bound)
+  // two steps per launch: the buffer written holds the state after both; runs of
+  // 64 launches go as replays of a captured graph (small lattices are launch-bound)
   if (c->fuse == 2) {
-    while (left >= 2 * kGraphMinLaunches) {
-      const int k = (int)std::min<int64_t>(left / 2, kGraphMaxLaunches);
+    while (left >= 2 * kGraphLaunches) {
+      const int k = kGraphLaunches;
       hipGraphExec_t exec = nullptr;
       lbm_status st = step2_graph(c, k, &exec);
       if (st != LBM_OK) return st;
