@@ -46,9 +46,9 @@ ALU_PEAK_TFLOPS = {"fp32": 78.6, "fp64": 78.6}
 FLOPS_PER_LU = 260  # FP arithmetic of one cell update in the single-step kernel's ISA
 # HBM bytes per launch of the two-step kernel in the default shape on 4096^2,
 # from rocprofv3 FETCH_SIZE + WRITE_SIZE (scaled by the copy calibration)
-MEASURED_TRAFFIC = {("fp32", 256, 16): (780.4e6 + 618.3e6), ("fp64", 256, 24): (1500.4e6 + 1218.4e6)}
+MEASURED_TRAFFIC = {("fp32", 256, 16): (788.7e6 + 619.2e6), ("fp64", 256, 69): (1356.0e6 + 1219.8e6)}
 # VALU issue utilisation of the same launches (SQ_INSTS_VALU against 256 CUs x GRBM_GUI_ACTIVE / 8)
-MEASURED_VALU_ISSUE = {("fp32", 256, 16): 0.801, ("fp64", 256, 24): 0.474}
+MEASURED_VALU_ISSUE = {("fp32", 256, 16): 0.796, ("fp64", 256, 69): 0.456}
 N = 4096
 RHO_MEAN = 0.183713  # (rho_v + rho_l)/2 of CS at 0.7Tc: (0.00929415 + 0.35813094)/2
 WORKLOAD = dict(nx=N, ny=N, eos="cs", T_over_Tc=0.7, A=-0.5, kappa=0.0)
