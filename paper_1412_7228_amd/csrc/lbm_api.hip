@@ -375,8 +375,9 @@ void default_launch(const lbm_params& p, int* tx, int* ty) {
 // smaller workgroups finish the grid sooner there (measured, alternating the
 // two shapes: 4096 x 520, 128 x 8 is 3% faster than 256 x 8; 2048^2 and
 // 4096 x 1024, 128 x 16 is 1.5% faster than 256 x 16; 1024^2, 128 x 8 is 6%
-// faster).  On 4096^2 the 256-lane shapes of 14 to 28 rows are within 1.5% of
-// each other in FP32, 16 to 32 in FP64.
+// faster).  On 4096^2 the 256-lane FP32 shapes of 12 to 28 rows are within 1.5%
+// of each other (16 rows fastest).  FP64 lattices at least 250 columns wide take
+// the whole-wave rule below instead.
 void default_launch2(const lbm_params& p, int* tx, int* ty) {
   int cus = 0, dev = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
@@ -397,12 +398,14 @@ void default_launch2(const lbm_params& p, int* tx, int* ty) {
     if (blocks(256, rows) >= 8ll * cus) w = 256;
   }
   if (w == 128) rows = rows_for(128, p.nx >= 250 ? 8ll * cus : 4ll * cus);
-  if (w == 256 && p.precision == LBM_FP64) {
+  if (p.precision == LBM_FP64 && p.nx >= 250) {
     // FP64: two 256-lane workgroups fit on a CU (62 KB of LDS each), so the grid
     // runs in few, long waves and a partly filled last wave costs much: take the
-    // smallest whole number of waves whose row blocks are 24 to 72 rows tall
-    // (4096^2: 60 x 17 = 1020 workgroups of 69 rows, two waves, 3.5% faster than
-    // 24 rows; 64 rows, 2.1 waves, is 8% slower)
+    // smallest whole number of waves whose row blocks are at most 72 rows tall
+    // (and at least 8).  Measured against the shapes above: 4096^2, 256 x 69
+    // (two waves) 3.5% faster than 256 x 24, while 256 x 64 (2.1 waves) is 8%
+    // slower; 8192^2, 256 x 67 +4%; 2048^2, 256 x 37 (one wave) +10%;
+    // 4096 x 520, 256 x 18 +14%.
     const long long slots = 2ll * cus;
     const long long ns = (p.nx + 256 - kStep2Halo - 1) / (256 - kStep2Halo);
     for (int k = 1; k <= 64; ++k) {
@@ -410,7 +413,10 @@ void default_launch2(const lbm_params& p, int* tx, int* ty) {
       if (rb < 1) continue;
       const long long t = (p.ny + rb - 1) / rb;
       if (t > 72) continue;
-      if (t >= 24) rows = (int)t;
+      if (t >= 8) {
+        w = 256;
+        rows = (int)t;
+      }
       break;
     }
   }

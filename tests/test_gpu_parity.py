@@ -524,7 +524,8 @@ def test_zero_steps_change_nothing_and_negative_counts_are_refused(lbm):
 
 @pytest.mark.parametrize("nx,ny,precision,expect", [
     (4096, 4096, "fp32", (256, 16, 2)), (4096, 4096, "fp64", (256, 69, 2)), (8192, 8192, "fp64", (256, 67, 2)),
-    (4096, 520, "fp32", (128, 8, 2)), (2048, 2048, "fp32", (128, 16, 2)), (200, 200, "fp32", (128, 8, 2))])
+    (4096, 520, "fp32", (128, 8, 2)), (2048, 2048, "fp32", (128, 16, 2)), (200, 200, "fp32", (128, 8, 2)),
+    (2048, 2048, "fp64", (256, 37, 2)), (4096, 520, "fp64", (256, 18, 2))])
 def test_default_launch_shape(lbm, nx, ny, precision, expect):
     """The default two-step launch on a 256-CU device: 256-lane strips where they give 8
     or more workgroups per CU, else 128-lane strips with rows down to 8; FP64 with
