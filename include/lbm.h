@@ -121,7 +121,11 @@ typedef struct {
  *     step count ends with one single-step launch of the default shape.
  * tile_y >= 1.  0 in a tile field selects the library default for the
  * lattice; steps_per_pass 0 selects 2, or 1 with tile_x = 64.  New contexts
- * start with two steps per pass and the default two-step shape. */
+ * start with two steps per pass and the default two-step shape: 256-lane
+ * strips of 16 rows (FP32) where they give at least 8 workgroups per CU,
+ * else 128-lane strips of 16 down to 8 rows; FP64 lattices at least 250
+ * columns wide take 256-lane row blocks (8 to 72 rows) that fill a whole
+ * number of waves of the device (two such workgroups per CU). */
 typedef struct {
   int32_t tile_x, tile_y;
   int32_t steps_per_pass;
