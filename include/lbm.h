@@ -278,9 +278,10 @@ typedef struct {
 
 /* Creates a batch of n domains with parameters params[0..n).  Allocates one
  * arena for all distribution buffers.  hip_stream as in lbm_create; on a
- * non-NULL stream the steps are enqueued as HIP graphs (the persistent mode's
- * counter reset + launch, or chunks of up to 64 per-step launches), on the
- * null stream as plain launches.
+ * non-NULL stream the steps of one lbm_batch_step call are enqueued as one
+ * HIP graph launch (the persistent mode's counter reset + launch, or all the
+ * per-step launches of up to 32,768 steps; the graph is cached for the next
+ * call with the same step count), on the null stream as plain launches.
  * LBM_EINVAL if a domain's parameters are invalid or the EOS kinds or
  * precisions differ. Default launch: LBM_BATCH_PER_STEP with two steps per
  * launch, 256 x 16 tiles. */

@@ -1307,11 +1307,13 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t n) {
   for (int d = 0; d < b->n; ++d)
     if (!b->inited[d]) return fail(LBM_ESTATE, "batch domain %d not initialised", d);
   // persistent mode: the whole call is one launch, chunked only where a group's
-  // queue (tiles x steps) would pass 2^31; per-step mode: graphs of up to 64
-  // launches
+  // queue (tiles x steps) would pass 2^31; per-step mode: one graph per call of
+  // up to 32,768 steps (the 20,000 steps of a droplet study are one graph launch
+  // of 10,000 kernel nodes; capturing and instantiating it takes about 20 ms and
+  // its replay runs as fast as shorter graphs)
   const int64_t chunk = b->mode == LBM_BATCH_PERSISTENT
                             ? std::max<int64_t>(1, ((1ll << 31) - 1) / b->max_group_tiles)
-                            : 64;
+                            : 32768;
   int64_t left = n;
   while (left > 0) {
     const int k = (int)std::min(left, chunk);

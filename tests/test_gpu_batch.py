@@ -236,3 +236,22 @@ def test_failing_domain_leaves_the_others_untouched(lbm, steps_per_pass):
         lat.init_field(rho[i])
         lat.step(40)
         assert np.array_equal(b.f_soa(i), lat.f_soa()), i
+
+
+def test_one_graph_per_call_replayed(lbm):
+    """All the launches of one lbm_batch_step call form one HIP graph, cached and replayed
+    for the next call with the same step count (here 500 launches, replayed twice, with
+    read-backs between): the domains stay bitwise the lattices run alone."""
+    say("batch: one graph of 1000 steps, replayed")
+    cfgs = _cfgs("fp32")
+    b = lbm.Batch(cfgs)
+    for i, d in enumerate(DOMAINS):
+        b.init_field(i, _rho0(i, d))
+    for rep in range(3):
+        b.step(1000)
+        b.observables()
+    for i, (c, d) in enumerate(zip(cfgs, DOMAINS)):
+        lat = lbm.Lattice(c)
+        lat.init_field(_rho0(i, d))
+        lat.step(3000)
+        assert np.array_equal(b.f_soa(i), lat.f_soa()), i
