@@ -165,7 +165,7 @@ double bisect(F f, double lo, double hi, int iters = 200) {
   return 0.5 * (lo + hi);
 }
 
-// 64-point Gauss-Legendre on [a, b] split into n panels.
+// Gauss-Legendre with 16 points on each of n equal panels of [a, b].
 template <typename F>
 double integrate(F f, double a, double b, int n = 64) {
   static const double xg[8] = {0.0950125098376374, 0.2816035507792589, 0.4580167776572274,
