@@ -255,3 +255,66 @@ def test_one_graph_per_call_replayed(lbm):
         lat.init_field(_rho0(i, d))
         lat.step(3000)
         assert np.array_equal(b.f_soa(i), lat.f_soa()), i
+
+
+def test_full_size_uneven_batch_sampled_domains(lbm, oracle_mod):
+    """The uneven batch at full size (256 droplets, sides 64-512, 24.3 M cells, FP32) in
+    the library's default batch launch (two steps per launch, 256 x 16 tiles, one graph
+    per call), 201 steps (100 two-step launches and a single step).  The draws reach
+    T/Tc = 0.6, below the lowest temperature at which the method stays stable for these
+    A (about 0.69 Tc at A = -0.5, Sec. 3.1.2), so some drops fail (each reported through
+    its own domain's observables); every domain without a fault keeps its mass,
+    five sampled domains (the smallest, the largest and three drawn) are bitwise the
+    same lattice run alone, and the smallest domain without a fault matches the FP64
+    oracle.  Densities start from the oracle's Maxwell construction for each draw."""
+    draws = inputs.batch_draws(256, 3)
+    say("uneven batch, 256 domains, 201 steps")
+    e = th.carnahan_starling()
+    _, Tc = th.critical_point(e)
+    cfgs, rhos = [], []
+    for d in draws:
+        rv, rl = th.maxwell(e, d["T_over_Tc"] * Tc)
+        cfgs.append(dict(nx=d["nx"], ny=d["ny"], eos="cs", T_over_Tc=d["T_over_Tc"], A=d["A"],
+                         kappa=d["kappa"], precision="fp32"))
+        rhos.append(inputs.droplet(d["nx"], d["ny"], d["R"], rl, rv, W=5.0, noise=1e-3, seed=d["seed"]))
+    cells = sum(c["nx"] * c["ny"] for c in cfgs)
+    assert 24_000_000 < cells < 26_000_000
+    b = lbm.Batch(cfgs)
+    launch = b.launch
+    assert (launch["mode"], launch["tile_x"], launch["tile_y"], launch["steps_per_pass"]) == \
+        ("per_step", 256, 16, 2)
+    for i, r in enumerate(rhos):
+        b.init_field(i, r)
+    m0 = np.array([o["mass"] for o in b.observables()])
+    steps = 201
+    b.step(steps)
+    obs = b.observables()
+    assert all(o["step"] == steps for o in obs)
+    ok = [i for i, o in enumerate(obs) if o["n_nonfinite"] == 0 and o["n_domain"] == 0]
+    say(f"  {len(ok)} of 256 domains without a fault after {steps} steps; failed at T/Tc "
+        f"{sorted(round(cfgs[i]['T_over_Tc'], 3) for i in range(256) if i not in ok)}")
+    assert len(ok) > 128
+    # Sec. 3.1.2: stable down to 0.69 Tc at A = -0.5 and 0.79 Tc at A = +0.5, so for the
+    # draws' A <= -0.3 a drop at 0.72 Tc or above must not fail
+    assert all(cfgs[i]["T_over_Tc"] < 0.72 for i in range(256) if i not in ok)
+    m1 = np.array([obs[i]["mass"] for i in ok])
+    assert np.abs(m1 / m0[ok] - 1).max() < 1e-6
+    sides = [c["nx"] for c in cfgs]
+    small, large = int(np.argmin(sides)), int(np.argmax(sides))
+    picks = [small, large] + [int(i) for i in np.random.default_rng(11).choice(256, 3, replace=False)]
+    for i in picks:
+        say(f"  domain {i}: {cfgs[i]['nx']}^2 against the lattice run alone")
+        lat = lbm.Lattice(cfgs[i])
+        lat.init_field(rhos[i])
+        lat.step(steps)
+        assert np.array_equal(b.f_soa(i), lat.f_soa(), equal_nan=True), i
+        lat.close()
+    small = min(ok, key=lambda i: sides[i])
+    say(f"  domain {small}: {cfgs[small]['nx']}^2 against the FP64 oracle")
+    o = oracle_mod.Oracle({k: v for k, v in cfgs[small].items() if k != "precision"}, nthreads=8)
+    o.init_field(rhos[small])
+    o.run(steps)
+    want = o.fields()["rho"]
+    got = b.field(small, "rho")
+    assert float(np.abs(got - want).max() / np.abs(want).max()) < 1e-5
+    b.close()
