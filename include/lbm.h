@@ -148,6 +148,17 @@ lbm_status lbm_critical_temperature(const lbm_params* p, double* Tc);
  * Eq. (17).  LBM_EINVAL for IDEAL, T/Tc outside (0, 1) or no bracket. */
 lbm_status lbm_coexistence(const lbm_params* p, double* rho_v, double* rho_l);
 
+/* Laplace law over several drops (Eq. 22; the test of Sec. 3.1.1 and Sec. 4.1):
+ * the least-squares slope through the origin of dp against 1/R_e,
+ *   *sigma = sum(dp_i / R_i) / sum(1 / R_i^2),
+ * and, if spread is not NULL, the relative spread of dp_i R_i over the drops,
+ *   *spread = (max - min) / |mean|.
+ * dp, R_e: n host doubles each (the lbm_obs fields of the same names), read
+ * only, owned by the caller.  Host arithmetic in FP64; no device use.
+ * LBM_EINVAL on NULL dp, R_e or sigma, n < 1, or a drop with R_e <= 0 or a
+ * non-finite dp or R_e (outputs then unchanged). */
+lbm_status lbm_laplace_fit(const double* dp, const double* R_e, int32_t n, double* sigma, double* spread);
+
 /* Bytes of one distribution buffer for these parameters (0 if invalid). */
 size_t lbm_buffer_bytes(const lbm_params* p);
 

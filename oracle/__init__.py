@@ -10,6 +10,7 @@ TEST INFRASTRUCTURE ONLY.  The product path never imports this package: only
   leading-order surface tension (Eqs. 14, 20, 28) and the exact discrete
   flat-interface balance.
 * ``mlp``           -- FP64 forward/backward of the surrogate network.
+* :func:`laplace_fit` -- the Laplace law (Eq. 22) fitted over several drops.
 
 A physical configuration is a plain dict with keys
 ``nx, ny, eos ('ideal'|'cs'|'vdw'|'pr'), a, b, R, omega_pr, K, T_over_Tc, A,
@@ -221,3 +222,23 @@ def moment_matrix() -> tuple[np.ndarray, np.ndarray]:
     M, Minv = np.empty(81), np.empty(81)
     lib.orc_moment_matrix(_ptr(M), _ptr(Minv))
     return M.reshape(9, 9), Minv.reshape(9, 9)
+
+
+def laplace_fit(dp, R) -> tuple[float, float]:
+    """Eq. (22), as tested over drop sizes in Sec. 3.1.1 and Sec. 4.1: dp = sigma / R.
+    sigma is the least-squares fit of that line through the origin, i.e. the sigma
+    minimising sum_i (dp_i - sigma x_i)^2 with x_i = 1 / R_i, whose normal equation
+    gives sigma = sum_i dp_i x_i / sum_i x_i^2.  Also returns how far the drops are
+    from one sigma: (max - min) / |mean| of dp_i R_i."""
+    dp = [float(v) for v in dp]
+    R = [float(v) for v in R]
+    if not dp or len(dp) != len(R) or any(not r > 0.0 for r in R):
+        raise ValueError("laplace_fit needs as many positive radii as pressure jumps (at least one)")
+    num = den = 0.0
+    for d, r in zip(dp, R):
+        x = 1.0 / r
+        num += d * x
+        den += x * x
+    each = [d * r for d, r in zip(dp, R)]
+    mean = sum(each) / len(each)
+    return num / den, (max(each) - min(each)) / abs(mean)

@@ -624,6 +624,26 @@ lbm_status lbm_coexistence(const lbm_params* p, double* rho_v, double* rho_l) {
   return coexistence(*p, rho_v, rho_l);
 }
 
+lbm_status lbm_laplace_fit(const double* dp, const double* R_e, int32_t n, double* sigma, double* spread) {
+  if (!dp || !R_e || !sigma) return fail(LBM_EINVAL, "NULL argument");
+  if (n < 1) return fail(LBM_EINVAL, "Laplace fit needs at least one drop (n = %d)", n);
+  double sxy = 0.0, sxx = 0.0, smin = HUGE_VAL, smax = -HUGE_VAL, ssum = 0.0;
+  for (int32_t i = 0; i < n; ++i) {
+    if (!(R_e[i] > 0.0) || !std::isfinite(R_e[i]) || !std::isfinite(dp[i]))
+      return fail(LBM_EINVAL, "Laplace fit: drop %d has R_e = %g, dp = %g", i, R_e[i], dp[i]);
+    const double x = 1.0 / R_e[i];
+    sxy += dp[i] * x;
+    sxx += x * x;
+    const double s = dp[i] * R_e[i];
+    smin = std::min(smin, s);
+    smax = std::max(smax, s);
+    ssum += s;
+  }
+  *sigma = sxy / sxx;
+  if (spread) *spread = (smax - smin) / std::fabs(ssum / n);
+  return LBM_OK;
+}
+
 size_t lbm_buffer_bytes(const lbm_params* p) {
   if (validate(p) != LBM_OK) return 0;
   return 9 * (size_t)p->ny * pitch_of(*p) * elem_size(*p);

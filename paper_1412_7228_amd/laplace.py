@@ -37,15 +37,17 @@ def initial_density(case: dict, cfg: dict) -> np.ndarray:
 
 
 def run_cases(cases: list, steps: int, precision: str = "fp32", mode: str = "per_step",
-              tile: tuple = (128, 16), chunk: int = 5000, steps_per_pass: int = 2) -> list:
+              tile: tuple = (128, 16), chunk: int = 5000, steps_per_pass: int = 2,
+              rhos: list | None = None) -> list:
     """Runs every case for `steps` steps in one batch; returns one result dict per case
     (the observables plus ``ok``: finite, positive densities, no U > 0 cell, a drop
-    denser than its surroundings)."""
+    denser than its surroundings).  ``rhos``: initial densities, one per case (default:
+    :func:`initial_density`)."""
     cfgs = [case_config(c, precision) for c in cases]
     b = lbm.Batch(cfgs)
     b.set_launch(mode, *tile, steps_per_pass=steps_per_pass)
     for i, (c, cfg) in enumerate(zip(cases, cfgs)):
-        b.init_field(i, initial_density(c, cfg))
+        b.init_field(i, initial_density(c, cfg) if rhos is None else rhos[i])
     left = steps
     while left > 0:
         k = min(chunk, left)
@@ -62,13 +64,9 @@ def run_cases(cases: list, steps: int, precision: str = "fp32", mode: str = "per
 
 
 def laplace_sigma(results: list) -> tuple[float, float]:
-    """Least-squares sigma through the origin of dp = sigma / R_e, and the relative
-    spread of dp * R_e over the radii."""
-    dp = np.array([r["dp"] for r in results])
-    inv_r = 1.0 / np.array([r["R_e"] for r in results])
-    sigma = float(np.sum(dp * inv_r) / np.sum(inv_r * inv_r))
-    s = dp / inv_r
-    return sigma, float((s.max() - s.min()) / abs(s.mean()))
+    """The library's Laplace fit (lbm_laplace_fit) of the results' dp and R_e: sigma
+    through the origin of dp = sigma / R_e, and the relative spread of dp * R_e."""
+    return lbm.laplace_fit([r["dp"] for r in results], [r["R_e"] for r in results])
 
 
 def sweep_cases(radii=(20, 30, 40, 50, 60), temps=(0.6, 0.7, 0.8), kappas=(0.0, 0.3, 0.6),

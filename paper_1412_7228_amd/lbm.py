@@ -105,6 +105,7 @@ def load_library(path: str | None = None):
         "lbm_params_default": (st, [P]),
         "lbm_critical_temperature": (st, [P, dp]),
         "lbm_coexistence": (st, [P, dp, dp]),
+        "lbm_laplace_fit": (st, [dp, dp, ctypes.c_int32, dp, dp]),
         "lbm_buffer_bytes": (ctypes.c_size_t, [P]),
         "lbm_create": (st, [P, vp, ctypes.POINTER(vp)]),
         "lbm_create_ext": (st, [P, vp, vp, vp, ctypes.c_size_t, ctypes.POINTER(vp)]),
@@ -184,6 +185,19 @@ def coexistence(cfg: dict) -> tuple[float, float]:
     rv, rl = ctypes.c_double(), ctypes.c_double()
     _check(lib.lbm_coexistence(ctypes.byref(p), ctypes.byref(rv), ctypes.byref(rl)))
     return rv.value, rl.value
+
+
+def laplace_fit(dp, R_e) -> tuple[float, float]:
+    """Laplace law over drops (lbm_laplace_fit): sigma as the least-squares slope of dp
+    against 1/R_e through the origin, and the relative spread of dp * R_e."""
+    lib = load_library()
+    d = np.ascontiguousarray(dp, dtype=np.float64).ravel()
+    r = np.ascontiguousarray(R_e, dtype=np.float64).ravel()
+    if d.size != r.size:
+        raise ValueError("dp and R_e differ in length")
+    sig, spread = ctypes.c_double(), ctypes.c_double()
+    _check(lib.lbm_laplace_fit(_dptr(d), _dptr(r), int(d.size), ctypes.byref(sig), ctypes.byref(spread)))
+    return sig.value, spread.value
 
 
 def _dptr(a: np.ndarray):

@@ -132,3 +132,20 @@ def test_largest_plane_is_accepted_and_one_more_row_is_not(lib):
     h = ctypes.c_void_p()
     assert lib.lbm_create(ctypes.byref(bad), None, ctypes.byref(h)) == -1
     assert b"4 GiB" in lib.lbm_last_error()
+
+
+def test_library_laplace_fit_matches_oracle(lib, oracle_mod):
+    """lbm_laplace_fit (host FP64) against the oracle's fit on scattered drops, and its
+    argument checks: no drop, a radius <= 0, a non-finite dp or radius."""
+    import numpy as np
+
+    rng = np.random.default_rng(9)
+    R = rng.uniform(10.0, 80.0, 7)
+    dp = 0.02 / R * (1 + 0.03 * rng.standard_normal(7))
+    s, spread = lbm.laplace_fit(dp, R)
+    s_o, spread_o = oracle_mod.laplace_fit(dp, R)
+    assert abs(s / s_o - 1) < 1e-14 and abs(spread / spread_o - 1) < 1e-12
+    for bad_dp, bad_r in (([], []), ([1e-3], [0.0]), ([1e-3], [-5.0]), ([float("nan")], [20.0]),
+                          ([1e-3], [float("inf")])):
+        with pytest.raises(lbm.LBMError):
+            lbm.laplace_fit(bad_dp, bad_r)

@@ -202,3 +202,23 @@ def test_ideal_gas_has_no_interaction(oracle_mod):
     got = o.interaction(np.random.default_rng(0).uniform(0.5, 1.5, (4, 5)))
     for k in ("U", "psi", "Fx", "Fy", "Qxx", "Qyy", "Qxy"):
         assert np.abs(got[k]).max() < 1e-16
+
+
+def test_laplace_fit_exact_line_least_squares_and_spread(oracle_mod):
+    """Eq. (22) over drop sizes: drops that obey dp = sigma / R exactly give sigma back
+    with zero spread; scattered drops give the slope that numpy's least squares finds
+    for the model dp = sigma x, x = 1/R; drops whose dp R are (0.9, 1, 1.1) sigma have a
+    spread of 0.2; a single drop gives dp R."""
+    R = np.array([20.0, 30.0, 40.0, 50.0, 60.0])
+    s, spread = oracle_mod.laplace_fit(0.0123 / R, R)
+    assert abs(s / 0.0123 - 1) < 1e-14 and spread < 1e-14
+    dp = 0.0123 / R * (1 + 0.05 * np.random.default_rng(5).standard_normal(R.size))
+    want = np.linalg.lstsq((1.0 / R)[:, None], dp, rcond=None)[0][0]
+    assert abs(oracle_mod.laplace_fit(dp, R)[0] / want - 1) < 1e-13
+    _, spread = oracle_mod.laplace_fit(np.array([0.9, 1.0, 1.1]) * 0.01 / R[:3], R[:3])
+    assert abs(spread - 0.2) < 1e-13
+    s, spread = oracle_mod.laplace_fit([2e-4], [25.0])
+    assert abs(s / (2e-4 * 25.0) - 1) < 1e-15 and spread == 0.0
+    for bad in (([], []), ([1e-3], [0.0]), ([1e-3, 2e-3], [20.0])):
+        with pytest.raises(ValueError):
+            oracle_mod.laplace_fit(*bad)
