@@ -22,7 +22,10 @@ bytes an unfused pair of single steps would have needed.  slab_share = the same
 kernel on one GPU's share of the lattice cut into 8 y-slabs (4096 x 512 rows
 plus 4 ghost rows per side), and the cost of refreshing the ghost rows.
 cpu_baseline = the FP64 CPU oracle on the host cores on a bounded sample of the
-same lattice.
+same lattice.  end_to_end = wall times from initial field to results (a 100^2
+FP64 droplet on the GPU and, as a second CPU baseline, on the oracle, both from
+one initial field; the 200^2 Laplace sweep; the benchmark lattice with its host
+transfers).  These two legs are the only ones that run the oracle.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -236,7 +239,10 @@ def end_to_end():
     from paper_1412_7228_amd import inputs, laplace, lbm
 
     cfg = dict(nx=100, ny=100, eos="cs", T_over_Tc=0.8, A=-0.5, kappa=0.0, precision="fp64")
-    rv, rl = lbm.coexistence(cfg)
+    # one initial field for both sides, between the oracle's Maxwell densities
+    e = oracle.thermo.carnahan_starling()
+    _, Tc = oracle.thermo.critical_point(e)
+    rv, rl = oracle.thermo.maxwell(e, 0.8 * Tc)
     rho = inputs.droplet(100, 100, 25.0, rl, rv, W=5.0, noise=1e-3, seed=0)
     torch.cuda.synchronize()
     t = time.perf_counter()
