@@ -188,14 +188,18 @@ lbm_status lbm_get_launch(const lbm_ctx* ctx, lbm_launch* launch);
 lbm_status lbm_init_field(lbm_ctx* ctx, const double* rho, const double* ux, const double* uy);
 
 /* Sets the distributions directly from a host array f[a][y][x] (9*nx*ny
- * doubles), rounded to the context precision.  Resets the step counter. */
+ * doubles, owned by the caller; copied before return), rounded to the context
+ * precision.  Resets the step counter.  LBM_EINVAL on NULL. */
 lbm_status lbm_set_distributions(lbm_ctx* ctx, const double* f);
 
 /* Enqueues n >= 0 time steps on the context stream and returns.  With two
  * steps per pass, each run of 64 two-step launches is a replay of a HIP graph
  * captured on a stream of the context's own (kernels only; cached per starting
  * buffer and launch shape) and the remaining launches go one by one; the
- * states are bitwise those of the launches issued one by one. */
+ * states are bitwise those of the launches issued one by one.  LBM_EINVAL for
+ * n < 0; LBM_ESTATE before the state is initialised or while a row-range
+ * launch (lbm_step_rows) is open; numerical faults surface at the next
+ * lbm_observables. */
 lbm_status lbm_step(lbm_ctx* ctx, int64_t n);
 
 /* Flag of lbm_step_rows: more row ranges of the same steps follow. */
@@ -249,8 +253,12 @@ lbm_status lbm_load_state(lbm_ctx* ctx, const void* buf, size_t len);
 /* Waits for the context stream (LBM_EDEVICE if a HIP call failed). */
 lbm_status lbm_sync(lbm_ctx* ctx);
 
-/* Current step count and the device pointer of the buffer that holds the
- * current state (for callers that time or inspect the device state). */
+/* Current step count, the device pointer of the buffer that holds the
+ * current state and its row pitch in elements (for callers that time or
+ * inspect the device state; layout [9][ny][pitch], post-collision values
+ * before streaming).  Each output may be NULL.  The buffer stays owned by the
+ * context (or the caller, after lbm_create_ext) and stops being current at
+ * the next step. */
 lbm_status lbm_state_info(const lbm_ctx* ctx, int64_t* step, const void** f_cur, int32_t* pitch);
 
 /* ---------------------------------------------------------------------------
