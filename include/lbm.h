@@ -309,7 +309,10 @@ void lbm_batch_destroy(lbm_batch* b);
 
 /* Chooses the launch mode and tile shape (re-plans the tiles and, in
  * persistent mode, their assignment to a grid no larger than the GPU holds
- * at once). */
+ * at once).  LBM_EINVAL for an invalid or switched-off choice (the batch then
+ * keeps its previous launch); LBM_ENOMEM or LBM_EDEVICE if the new tile lists
+ * cannot be placed on the device, after which lbm_batch_step refuses to run
+ * until a later call succeeds. */
 lbm_status lbm_batch_set_launch(lbm_batch* b, const lbm_batch_launch* launch);
 lbm_status lbm_batch_get_launch(const lbm_batch* b, lbm_batch_launch* launch);
 
@@ -317,8 +320,9 @@ lbm_status lbm_batch_get_launch(const lbm_batch* b, lbm_batch_launch* launch);
 lbm_status lbm_batch_init_field(lbm_batch* b, int32_t i, const double* rho, const double* ux,
                                 const double* uy);
 
-/* Enqueues n steps of every domain (asynchronous).  LBM_ESTATE if a domain is
- * not initialised. */
+/* Enqueues n steps of every domain (asynchronous).  LBM_EINVAL for n < 0;
+ * LBM_ESTATE if a domain is not initialised or the batch has no launch layout
+ * (a failed lbm_batch_set_launch). */
 lbm_status lbm_batch_step(lbm_batch* b, int64_t n);
 
 /* Waits for the batch; LBM_EDEVICE if a persistent launch aborted (a barrier

@@ -424,12 +424,13 @@ void default_launch2(const lbm_params& p, int* tx, int* ty) {
   *ty = std::min(rows, p.ny);
 }
 
+// Allocates whichever scratch buffer is still missing (after a failed
+// allocation the others stay, and the next call completes the set).
 lbm_status ensure_scratch(lbm_ctx* c) {
-  if (c->work) return LBM_OK;
   const size_t n = (size_t)c->p.nx * c->p.ny;
-  HIP_TRY(hipMalloc(&c->work, 4 * n * sizeof(double)));
-  HIP_TRY(hipMalloc(&c->partials, (size_t)obs_partials_count(c->g) * kNumRed * sizeof(double)));
-  HIP_TRY(hipMalloc(&c->red, (kNumRed + 2) * sizeof(double)));
+  if (!c->work) HIP_TRY(hipMalloc(&c->work, 4 * n * sizeof(double)));
+  if (!c->partials) HIP_TRY(hipMalloc(&c->partials, (size_t)obs_partials_count(c->g) * kNumRed * sizeof(double)));
+  if (!c->red) HIP_TRY(hipMalloc(&c->red, (kNumRed + 2) * sizeof(double)));
   return LBM_OK;
 }
 
@@ -942,6 +943,7 @@ struct lbm_batch {
   // state
   int parity = 0;
   int64_t step = 0;
+  bool layout_ok = false;  // the device tile lists match mode / tile / fuse
   // graph cache
   hipGraphExec_t exec = nullptr;
   int exec_mode = -1, exec_steps = 0, exec_parity = -1, exec_fuse = 0;
@@ -972,6 +974,7 @@ void batch_free_layout(lbm_batch* b) {
 // group) and the tiles are stored group by group, each domain's tiles
 // together, so that a group's queue finishes one domain's step before the next.
 lbm_status batch_layout(lbm_batch* b) {
+  b->layout_ok = false;  // until every list below is on the device
   HIP_TRY(hipStreamSynchronize(b->stream));
   batch_free_layout(b);
   HIP_TRY(hipMemsetAsync(b->d_err, 0, sizeof(int), b->stream));
@@ -1066,6 +1069,7 @@ lbm_status batch_layout(lbm_batch* b) {
   HIP_TRY(hipMemcpyAsync(b->d_group_begin, group_begin.data(), group_begin.size() * sizeof(int),
                          hipMemcpyHostToDevice, b->stream));
   HIP_TRY(hipStreamSynchronize(b->stream));
+  b->layout_ok = true;
   return LBM_OK;
 }
 
@@ -1145,16 +1149,16 @@ lbm_status batch_graph(lbm_batch* b, int n) {
 }
 
 lbm_status batch_scratch(lbm_batch* b) {
-  if (b->work) return LBM_OK;
+  if (b->work && b->partials && b->red) return LBM_OK;
   size_t cells = 0;
   int parts = 0;
   for (int d = 0; d < b->n; ++d) {
     cells = std::max(cells, (size_t)b->p[d].nx * b->p[d].ny);
     parts = std::max(parts, obs_partials_count(b->g[d]));
   }
-  HIP_TRY(hipMalloc(&b->work, 4 * cells * sizeof(double)));
-  HIP_TRY(hipMalloc(&b->partials, (size_t)parts * kNumRed * sizeof(double)));
-  HIP_TRY(hipMalloc(&b->red, (kNumRed + 2) * sizeof(double)));
+  if (!b->work) HIP_TRY(hipMalloc(&b->work, 4 * cells * sizeof(double)));
+  if (!b->partials) HIP_TRY(hipMalloc(&b->partials, (size_t)parts * kNumRed * sizeof(double)));
+  if (!b->red) HIP_TRY(hipMalloc(&b->red, (kNumRed + 2) * sizeof(double)));
   return LBM_OK;
 }
 
@@ -1326,6 +1330,8 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t n) {
   if (n < 0) return fail(LBM_EINVAL, "negative step count");
   for (int d = 0; d < b->n; ++d)
     if (!b->inited[d]) return fail(LBM_ESTATE, "batch domain %d not initialised", d);
+  if (!b->layout_ok)
+    return fail(LBM_ESTATE, "batch has no launch layout (the last lbm_batch_set_launch failed); set it again");
   // persistent mode: the whole call is one launch, chunked only where a group's
   // queue (tiles x steps) would pass 2^31; per-step mode: one graph per call of
   // up to 32,768 steps (the 20,000 steps of a droplet study are one graph launch
@@ -1521,8 +1527,11 @@ lbm_status lbm_mlp_train(lbm_mlp* m, int32_t iters, float lr, float* loss_out) {
   if (m->ndata < 1) return fail(LBM_ESTATE, "lbm_mlp_train before lbm_mlp_set_data");
   if (iters < 0 || !(lr > 0.f)) return fail(LBM_EINVAL, "iters must be >= 0 and lr > 0");
   if (iters > m->loss_cap) {
-    if (m->loss) HIP_TRY(hipFree(m->loss));
+    // forget the old buffer before anything can fail, so no later call uses it
+    float* old = m->loss;
     m->loss = nullptr;
+    m->loss_cap = 0;
+    if (old) HIP_TRY(hipFree(old));
     HIP_TRY(hipMalloc(&m->loss, (size_t)iters * 4));
     m->loss_cap = iters;
   }
