@@ -6,6 +6,7 @@ shapes, ragged sizes, every EOS, the U > 0 clamp and the full 4096^2 lattice in
 the benchmark's launch shape are covered.
 """
 import ctypes
+import json
 import os
 import sys
 
@@ -47,11 +48,29 @@ def rel(a, b, floor=1e-300):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), floor))
 
 
-def rel_field(k, a, b):
-    """Relative difference of a field.  Velocities are differences of O(rho) numbers
-    divided by rho, so their rounding floor is absolute (~1e-16 of the lattice speed);
-    they are measured against max(max|u|, 1e-3)."""
-    return rel(a, b, 1e-3 if k in ("ux", "uy") else 1e-300)
+def rel_field(k, a, b, label=""):
+    """Relative difference of a field against the field's own scale (max |oracle|), for
+    the velocities too; each velocity comparison is printed with that scale and the
+    absolute difference, so a run records what the bar measured."""
+    r = rel(a, b)
+    if k in ("ux", "uy"):
+        print("[velocity-error] " + json.dumps(dict(case=label, field=k, max_u=float(np.abs(b).max()),
+                                                    abs_err=float(np.abs(a - b).max()), rel_own_scale=r)),
+              flush=True)
+    return r
+
+
+def velocity_ok(gpu, orc, precision):
+    """The velocity bar.  FP64: within 1e-11 of the field's own maximum, with no floor.
+    FP32: v = (sum f e + F/2)/rho is a difference of O(rho) populations divided by rho,
+    so its rounding error is absolute, a few FP32 ulps of the lattice speed per step; it
+    is held to 2e-5 (the FP32 field bar) of max(max|v|, 0.01), i.e. relative where the
+    flow is at least 1% of the lattice speed and at most 2e-7 absolute below that."""
+    err = float(np.abs(gpu - orc).max())
+    scale = float(np.abs(orc).max())
+    if precision == "fp64":
+        return err <= 1e-11 * scale
+    return err <= 2e-5 * max(scale, 0.01)
 
 
 def oracle_fields(o):
@@ -93,12 +112,12 @@ def test_fp64_droplet_1000_steps(lbm, oracle_mod):
     o, lat = run_pair(lbm, oracle_mod, cfg, rho0, 1000)
     og, gg = oracle_fields(o), gpu_fields(lat)
     for k in FIELDS:
-        assert rel_field(k, gg[k], og[k]) < 1e-11, (k, rel_field(k, gg[k], og[k]))
+        r = rel_field(k, gg[k], og[k], "fp64 droplet 100x100 1000 steps")
+        assert r < 1e-11, (k, r)
     ob, gb = o.observables(), lat.observables()
-    for k in ("mass", "rho_in", "rho_out", "rho_min", "rho_max", "p_in", "p_out", "R_e"):
-        assert abs(gb[k] / ob[k] - 1) < 1e-11, k
+    for k in ("mass", "rho_in", "rho_out", "rho_min", "rho_max", "p_in", "p_out", "R_e", "max_u"):
+        assert abs(gb[k] / ob[k] - 1) < 1e-11, (k, gb[k], ob[k])
     assert abs(gb["dp"] - ob["dp"]) < 1e-11 * abs(ob["p_in"])
-    assert abs(gb["max_u"] / ob["max_u"] - 1) < 1e-9
     assert abs(gb["mom_x"] - ob["mom_x"]) < 1e-12 * ob["mass"]
     assert gb["n_domain"] == 0 and gb["n_nonfinite"] == 0 and gb["step"] == 1000
 
@@ -132,10 +151,13 @@ def test_ragged_shapes_every_eos(lbm, oracle_mod, nx, ny, eos, tile, precision):
     o, lat = run_pair(lbm, oracle_mod, cfg, rho0, 25, u0=u0, tile=tile)
     og, gg = oracle_fields(o), gpu_fields(lat)
     tol = 1e-12 if precision == "fp64" else 2e-5
+    label = f"ragged {nx}x{ny} {eos['eos']} {precision} 25 steps"
     for k in FIELDS:
-        if k in ("ux", "uy") and precision == "fp32":
-            continue  # velocities are differences of O(1) numbers; covered via f
-        assert rel_field(k, gg[k], og[k]) < tol, (k, rel_field(k, gg[k], og[k]))
+        r = rel_field(k, gg[k], og[k], label)
+        if k in ("ux", "uy"):
+            assert velocity_ok(gg[k], og[k], precision), (k, r)
+            continue
+        assert r < tol, (k, r)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
@@ -183,7 +205,7 @@ def test_domain_clamp_matches_oracle(lbm, oracle_mod):
     assert gb["status"] == -5 and gb["n_domain"] == ob["n_domain"] and gb["n_nonfinite"] == 0
     og, gg = oracle_fields(o), gpu_fields(lat)
     for k in FIELDS:
-        assert rel_field(k, gg[k], og[k]) < 1e-12, k
+        assert rel_field(k, gg[k], og[k], "U>0 clamp 48x40 3 steps") < 1e-12, k
 
 
 def test_nonfinite_initial_density_rejected(lbm):
@@ -272,9 +294,11 @@ def test_density_dependent_viscosity(lbm, oracle_mod, precision):
     og, gg = oracle_fields(o), gpu_fields(lat)
     tol = 1e-12 if precision == "fp64" else 2e-5
     for k in FIELDS:
-        if k in ("ux", "uy") and precision == "fp32":
+        r = rel_field(k, gg[k], og[k], f"variable viscosity 120x96 {precision} 300 steps")
+        if k in ("ux", "uy"):
+            assert velocity_ok(gg[k], og[k], precision), (k, r)
             continue
-        assert rel_field(k, gg[k], og[k]) < tol, (k, rel_field(k, gg[k], og[k]))
+        assert r < tol, (k, r)
 
 
 # ---------------------------------------------------------------------------

@@ -222,3 +222,59 @@ def test_laplace_fit_exact_line_least_squares_and_spread(oracle_mod):
     for bad in (([], []), ([1e-3], [0.0]), ([1e-3, 2e-3], [20.0])):
         with pytest.raises(ValueError):
             oracle_mod.laplace_fit(*bad)
+
+
+@pytest.mark.parametrize("eos,tr,rhos", [
+    ("cs", 0.8, np.linspace(0.005, 0.6, 24)),
+    ("vdw", 0.9, np.linspace(0.2, 9.0, 24)),
+    ("pr", 0.8, np.linspace(0.01, 8.5, 24)),
+    ("pr", 0.6, np.linspace(0.01, 9.0, 24)),
+    ("ideal", 0.0, np.linspace(0.1, 3.0, 24)),
+])
+def test_c_pressure_equals_thermo_pressure(oracle_mod, eos, tr, rhos):
+    """The C oracle's K p_EOS (used in every density pass) is the same function as the
+    thermodynamics module's (whose critical point, Maxwell construction and, for PR, the
+    acentric factor are pinned in the thermodynamics tests): every EOS at 24 densities
+    across both phases, with K = 0.5, to 1e-14 of the size of the pressure's two terms,
+    K (rho R T + a rho^2) (the pressure passes through zero between the phases, where the
+    terms cancel and a relative difference says nothing)."""
+    from oracle import thermo as th
+
+    cfg = dict(nx=3, ny=3, eos=eos, K=0.5, T_over_Tc=tr if tr else 0.8)
+    o = oracle_mod.Oracle(cfg)
+    if eos == "ideal":
+        want = rhos / 3.0
+        scale = want
+    else:
+        e = oracle_mod.eos_of(cfg)
+        T, Tc = oracle_mod.temperature(cfg)
+        want = np.asarray(e.p(rhos, T, Tc))
+        assert isinstance(e, th.EOS) and e.K == 0.5
+        scale = e.K * (rhos * e.R * T + e.a * rhos**2)
+    got = np.array([o.pressure(r) for r in rhos])
+    assert (np.abs(got - want) <= 1e-14 * scale).all(), np.max(np.abs(got - want) / scale)
+
+
+def test_initial_equilibrium_has_the_moments_of_eq4(oracle_mod):
+    """The oracle's initial state (orc_init_equilibrium, the second-order equilibrium in
+    velocity space) transformed by M equals the equilibrium moments of Eq. (4) written in
+    moment space, rho (1, -2 + 3|u|^2, 1 - 3|u|^2, ux, -ux, uy, -uy, ux^2 - uy^2, ux uy),
+    to 1e-14, including the velocity terms, at |u| up to about 0.14."""
+    M, _ = oracle_mod.moment_matrix()
+    g = np.random.default_rng(11)
+    n = 6
+    o = oracle_mod.Oracle(dict(nx=n, ny=n, eos="ideal"))
+    rho = g.uniform(0.05, 3.0, (n, n))
+    ux = g.uniform(-0.1, 0.1, (n, n))
+    uy = g.uniform(-0.1, 0.1, (n, n))
+    o.init_field(rho, ux, uy)
+    m = np.einsum("ka,yxa->yxk", M, o.f)
+    v2 = ux * ux + uy * uy
+    eq4 = rho[..., None] * np.stack([np.ones_like(ux), -2 + 3 * v2, 1 - 3 * v2, ux, -ux, uy, -uy,
+                                     ux * ux - uy * uy, ux * uy], axis=-1)
+    assert np.abs(m - eq4).max() < 1e-14 * rho.max()
+    # and the moments do not vanish: the test sees the velocity terms
+    assert np.abs(eq4[..., 3]).max() > 0.1 and np.abs(eq4[..., 8]).max() > 1e-3
+    # the read-out inverts it: v = (sum f e + F/2)/rho with F = 0 for the ideal gas
+    fl = o.fields()
+    assert np.abs(fl["ux"] - ux).max() < 1e-15 and np.abs(fl["uy"] - uy).max() < 1e-15

@@ -159,3 +159,80 @@ def test_lowest_temperature_density_ratios():
     assert ratios[0.81] < g["density_ratio"][1] < ratios[0.79]
     with pytest.raises(RuntimeError):
         th.discrete_flat_balance(e, 0.69 * Tc, g["A"][1], N=100)
+
+
+def _pr_constants():
+    g = GOLDEN["peng_robinson"]
+    return g, th.EOS("pr", 2.0 / 49.0, g["b"], g["R"], 1.0, g["omega"])
+
+
+def test_peng_robinson_critical_point_eq29_relations():
+    """Sec. 4 under Eq. (29): a = 0.45724 R^2 Tc^2 / p_c and b = 0.0778 R Tc / p_c.  Eliminating
+    p_c gives Tc = (0.0778 / 0.45724) a / (b R), and then p_c = 0.0778 R Tc / b.  The oracle's
+    critical point (dp/drho = d2p/drho2 = 0 of Eq. 29 with alpha(Tc) = 1) must satisfy both
+    within what the printed rounding of the two coefficients allows (half a unit in their last
+    digit: 6.4e-4 relative for 0.0778, 1.1e-5 for 0.45724)."""
+    g, e = _pr_constants()
+    rc, Tc = th.critical_point(e)
+    ca, cb = g["a_coefficient"], g["b_coefficient"]
+    bound = 0.5e-4 / cb + 0.5e-5 / ca
+    Tc_printed = (cb / ca) * e.a / (e.b * e.R)
+    assert abs(Tc / Tc_printed - 1) < bound, (Tc, Tc_printed)
+    pc = float(e.p(rc, Tc, Tc))
+    assert abs(pc / (cb * e.R * Tc / e.b) - 1) < bound
+    assert abs(e.a / (ca * e.R**2 * Tc**2 / pc) - 1) < 2 * bound
+    # the critical isotherm is flat with an inflection there
+    assert abs(float(e.dp(rc, Tc, Tc))) < 1e-12 and abs(float(e.d2p(rc, Tc, Tc))) < 1e-9
+    # textbook Peng-Robinson critical compressibility Z_c = p_c / (rho_c R T_c) = 0.3074
+    assert abs(pc / (rc * e.R * Tc) - 0.3074) < 1e-4
+    # K scales the pressure only, not the critical temperature
+    _, Tc_k = th.critical_point(th.EOS("pr", e.a, e.b, e.R, 0.5, e.omega))
+    assert abs(Tc_k / Tc - 1) < 1e-12
+
+
+@pytest.mark.parametrize("omega", [0.0, 0.2, 0.344, 0.5])
+def test_peng_robinson_alpha_reproduces_the_acentric_factor(omega):
+    """alpha(T) of Eq. (29) is the Peng-Robinson temperature function fitted so that the EOS
+    gives back the acentric factor omega_0 it is built from.  Pitzer's definition of the
+    acentric factor (textbook, independent of Eq. 29): omega = -1 - log10(p_sat(0.7 Tc) / p_c).
+    The Maxwell saturation pressure of the oracle's PR isotherm at 0.7 Tc must return omega
+    within 0.005 (a change of 0.005 in omega is one of about 0.008 in the coefficient of
+    alpha, so a wrong coefficient, a dropped omega^2 term or sqrt(T/Tc) read as T/Tc fails)."""
+    g, e0 = _pr_constants()
+    e = th.EOS("pr", e0.a, e0.b, e0.R, 1.0, omega)
+    rc, Tc = th.critical_point(e)
+    pc = float(e.p(rc, Tc, Tc))
+    rv, rl = th.maxwell(e, 0.7 * Tc, Tc)
+    psat = float(e.p(rv, 0.7 * Tc, Tc))
+    assert abs(float(e.p(rl, 0.7 * Tc, Tc)) / psat - 1) < 1e-9
+    assert abs(-1.0 - math.log10(psat / pc) - omega) < 5e-3
+
+
+def test_peng_robinson_maxwell_matches_chemical_potential_equality():
+    """Independent formulation of PR coexistence at the Sec. 4 state (0.8 Tc): equal pressure
+    and equal chemical potential, mu from the PR Helmholtz free energy
+    f = R T rho ln(rho/(1 - b rho)) - (a alpha rho / (2 sqrt2 b)) ln((1 + (1+sqrt2) b rho) / (1 + (1-sqrt2) b rho))."""
+    g, e = _pr_constants()
+    _, Tc = th.critical_point(e)
+    T = 0.8 * Tc
+    rv, rl = th.maxwell(e, T, Tc)
+    k = 0.37464 + 1.54226 * e.omega - 0.26992 * e.omega**2
+    aa = e.a * (1 + k * (1 - math.sqrt(0.8))) ** 2
+    b, s2 = e.b, math.sqrt(2.0)
+
+    def free(r):
+        return (T * r * math.log(r / (1 - b * r))
+                - aa * r / (2 * s2 * b) * math.log((1 + (1 + s2) * b * r) / (1 + (1 - s2) * b * r)))
+
+    def mu(r):  # d free / d rho
+        lp, lm = 1 + (1 + s2) * b * r, 1 + (1 - s2) * b * r
+        L = math.log(lp / lm)
+        dL = (1 + s2) * b / lp - (1 - s2) * b / lm
+        return T * math.log(r / (1 - b * r)) + T / (1 - b * r) - aa / (2 * s2 * b) * (L + r * dL)
+
+    def p(r):
+        return r * mu(r) - free(r)
+
+    sol = optimize.fsolve(lambda v: [p(v[0]) - p(v[1]), mu(v[0]) - mu(v[1])], [rv * 1.01, rl * 0.99],
+                          xtol=1e-14)
+    assert abs(sol[0] / rv - 1) < 1e-9 and abs(sol[1] / rl - 1) < 1e-9
