@@ -233,6 +233,25 @@ lbm_status lbm_step_rows(lbm_ctx* ctx, int32_t n, int32_t y_begin, int32_t rows,
  * LBM_EDOMAIN (after filling *out) if the state holds such cells. */
 lbm_status lbm_observables(lbm_ctx* ctx, lbm_obs* out);
 
+/* lbm_observables for callers that cannot allocate device memory (code run
+ * between HIP graph captures, tight serving loops, harnesses that forbid
+ * hipMalloc): the same FP64 observables, bitwise, with nothing allocated by
+ * the call or lazily for it.  It keeps no per-cell field arrays (each cell's
+ * neighbourhood is recomputed from the distributions) and puts its partial
+ * sums in a file-scope device array of the library: 4 MiB on each GPU it runs
+ * on, held until the process ends, shared by every context on that GPU and
+ * keeping the last call's contents (every call overwrites what it reads).
+ * Calls that overlapped on one GPU would race on that array; the library
+ * serialises its own calls with a process-wide lock held until the call's
+ * stream has finished with the array.  Synchronises the context stream.
+ * Errors: LBM_EINVAL on NULL or for a lattice of more than
+ * lbm_noalloc_max_cells() cells (checked first), LBM_ESTATE before the state
+ * is initialised, LBM_EDEVICE if a HIP call fails; LBM_ENONFINITE and
+ * LBM_EDOMAIN as lbm_observables (after filling *out). */
+lbm_status lbm_observables_noalloc(lbm_ctx* ctx, lbm_obs* out);
+/* Largest lattice (nx * ny) that lbm_observables_noalloc accepts: 2^28. */
+int64_t lbm_noalloc_max_cells(void);
+
 /* Copies one field (lbm_field) of the current state to host out[y][x] in FP64
  * (nx*ny doubles, owned by the caller); synchronises the context stream.
  * LBM_EINVAL for an unknown field or NULL, LBM_ESTATE before the state is

@@ -10,6 +10,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -495,20 +496,13 @@ lbm_status check_density(const double* rho, size_t n) {
   return LBM_OK;
 }
 
-// FP64 observables of one state (shared by lattices and batch domains).
-lbm_status observe(const lbm_params& p, const ModelConsts& m, const Geometry& g, const void* f,
-                   int64_t step, double* work, double* partials, double* red, hipStream_t stream,
-                   lbm_obs* o) {
-  const lbm_precision prec = (lbm_precision)p.precision;
-  HIP_TRY(launch_density_fields(prec, g, m, f, work, stream));
-  HIP_TRY(launch_observables(prec, g, m, f, work, partials, red, stream));
+// The host part of the observables: h[0..kNumRed) the device reduction
+// (mass, momentum, density extremes, max |v|^2, fault counts), h[kNumRed] and
+// h[kNumRed + 1] rho at (nx/2, ny/2) and at (0, 0); pressures and the Laplace
+// quantities of Eq. 22 follow on the host in FP64.
+lbm_status finish_observables(const lbm_params& p, const ModelConsts& m, const double* h,
+                              int64_t step, lbm_obs* o) {
   const size_t n = (size_t)p.nx * p.ny;
-  const size_t i_in = (size_t)(p.ny / 2) * p.nx + p.nx / 2;
-  HIP_TRY(hipMemcpyAsync(red + kNumRed, work + i_in, sizeof(double), hipMemcpyDeviceToDevice, stream));
-  HIP_TRY(hipMemcpyAsync(red + kNumRed + 1, work, sizeof(double), hipMemcpyDeviceToDevice, stream));
-  double h[kNumRed + 2];
-  HIP_TRY(hipMemcpyAsync(h, red, sizeof h, hipMemcpyDeviceToHost, stream));
-  HIP_TRY(hipStreamSynchronize(stream));
   o->step = step;
   o->mass = h[0];
   o->mom_x = h[1];
@@ -529,6 +523,22 @@ lbm_status observe(const lbm_params& p, const ModelConsts& m, const Geometry& g,
   if (o->n_nonfinite > 0) return fail(LBM_ENONFINITE, "%lld cells with non-finite or non-positive density", (long long)o->n_nonfinite);
   if (o->n_domain > 0) return fail(LBM_EDOMAIN, "%lld cells with U > 0", (long long)o->n_domain);
   return LBM_OK;
+}
+
+// FP64 observables of one state (shared by lattices and batch domains).
+lbm_status observe(const lbm_params& p, const ModelConsts& m, const Geometry& g, const void* f,
+                   int64_t step, double* work, double* partials, double* red, hipStream_t stream,
+                   lbm_obs* o) {
+  const lbm_precision prec = (lbm_precision)p.precision;
+  HIP_TRY(launch_density_fields(prec, g, m, f, work, stream));
+  HIP_TRY(launch_observables(prec, g, m, f, work, partials, red, stream));
+  const size_t i_in = (size_t)(p.ny / 2) * p.nx + p.nx / 2;
+  HIP_TRY(hipMemcpyAsync(red + kNumRed, work + i_in, sizeof(double), hipMemcpyDeviceToDevice, stream));
+  HIP_TRY(hipMemcpyAsync(red + kNumRed + 1, work, sizeof(double), hipMemcpyDeviceToDevice, stream));
+  double h[kNumRed + 2];
+  HIP_TRY(hipMemcpyAsync(h, red, sizeof h, hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  return finish_observables(p, m, h, step, o);
 }
 
 lbm_status read_field(const lbm_params& p, const ModelConsts& m, const Geometry& g, const void* f,
@@ -830,6 +840,29 @@ lbm_status lbm_observables(lbm_ctx* c, lbm_obs* o) {
   if (st != LBM_OK) return st;
   return observe(c->p, c->m, c->g, c->buf[c->cur], c->step, c->work, c->partials, c->red, c->stream, o);
 }
+
+lbm_status lbm_observables_noalloc(lbm_ctx* c, lbm_obs* o) {
+  if (!c || !o) return fail(LBM_EINVAL, "NULL argument");
+  const long long cells = (long long)c->p.nx * c->p.ny;
+  if (cells > noalloc_max_cells())
+    return fail(LBM_EINVAL, "lbm_observables_noalloc: %lld cells exceed its scratch (at most %lld cells)",
+                cells, noalloc_max_cells());
+  if (!c->initialized) return fail(LBM_ESTATE, "observables before lbm_init_field");
+  // one call at a time in this process: every call on a device shares its scratch array
+  static std::mutex mu;
+  std::lock_guard<std::mutex> lock(mu);
+  double* scratch = nullptr;
+  HIP_TRY(noalloc_scratch(&scratch));
+  double* red = scratch + (size_t)obs_partials_count(c->g) * kNumRed;
+  HIP_TRY(launch_observables_direct((lbm_precision)c->p.precision, c->g, c->m, c->buf[c->cur], scratch,
+                                    red, c->stream));
+  double h[kNumRed + 2];
+  HIP_TRY(hipMemcpyAsync(h, red, sizeof h, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return finish_observables(c->p, c->m, h, c->step, o);
+}
+
+int64_t lbm_noalloc_max_cells(void) { return noalloc_max_cells(); }
 
 lbm_status lbm_get_field(lbm_ctx* c, int32_t which, double* out) {
   if (!c || !out) return fail(LBM_EINVAL, "NULL argument");

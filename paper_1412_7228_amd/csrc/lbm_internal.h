@@ -71,6 +71,16 @@ int obs_partials_count(const Geometry& g);
 hipError_t launch_observables(lbm_precision prec, const Geometry& g, const ModelConsts& m,
                               const void* f, const double* work, double* partials, double* red,
                               hipStream_t s);
+// The same reduction from the distributions alone (no field arrays), plus rho
+// at (nx/2, ny/2) and (0, 0) in red[kNumRed], red[kNumRed + 1]; bitwise the
+// results of launch_density_fields + launch_observables.
+hipError_t launch_observables_direct(lbm_precision prec, const Geometry& g, const ModelConsts& m,
+                                     const void* f, double* partials, double* red, hipStream_t s);
+// The device address of the file-scope scratch array of the current device
+// (kNumRed * (noalloc_max_cells() / 4096) + kNumRed + 2 doubles), resolved
+// once per device; and the largest lattice (cells) whose partials fit in it.
+hipError_t noalloc_scratch(double** out);
+long long noalloc_max_cells();
 
 // Batched engine (lbm_batch.hip).  Descriptors and tiles are opaque records
 // filled on the host and copied to the device.

@@ -117,6 +117,8 @@ def load_library(path: str | None = None):
         "lbm_step": (st, [vp, ctypes.c_int64]),
         "lbm_step_rows": (st, [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
         "lbm_observables": (st, [vp, ctypes.POINTER(Obs)]),
+        "lbm_observables_noalloc": (st, [vp, ctypes.POINTER(Obs)]),
+        "lbm_noalloc_max_cells": (ctypes.c_int64, []),
         "lbm_get_field": (st, [vp, ctypes.c_int32, dp]),
         "lbm_save_state": (st, [vp, vp, ctypes.POINTER(ctypes.c_size_t)]),
         "lbm_load_state": (st, [vp, vp, ctypes.c_size_t]),
@@ -289,9 +291,12 @@ class Lattice:
         _check(self.lib.lbm_sync(self.h))
 
     # -- read-out ------------------------------------------------------------
-    def observables(self, check: bool = True) -> dict:
+    def observables(self, check: bool = True, noalloc: bool = False) -> dict:
+        """FP64 observables (lbm_observables; ``noalloc``: lbm_observables_noalloc, the
+        variant that allocates nothing)."""
         o = Obs()
-        st = self.lib.lbm_observables(self.h, ctypes.byref(o))
+        fn = self.lib.lbm_observables_noalloc if noalloc else self.lib.lbm_observables
+        st = fn(self.h, ctypes.byref(o))
         if check:
             _check(st)
         d = {k: getattr(o, k) for k, _ in Obs._fields_}

@@ -42,6 +42,12 @@ def test_every_declared_symbol_is_exported(lib):
     assert not missing, missing
 
 
+def test_noalloc_limit_is_exported_without_a_device(lib):
+    """The size limit of lbm_observables_noalloc is a host constant: 2^28 cells."""
+    lib.lbm_noalloc_max_cells.restype = ctypes.c_int64
+    assert lib.lbm_noalloc_max_cells() == 2**28
+
+
 def test_defaults_and_strerror(lib):
     p = lbm.Params()
     assert lib.lbm_params_default(ctypes.byref(p)) == 0
