@@ -60,16 +60,19 @@ def _vdw_droplet_sigma(oracle_mod, A, kappa, ncpu, steps=8000):
 
 
 def test_sigma_vs_kappa_method2(oracle_mod, ncpu):
-    """Sec. 3.2.2: sigma = 0.0459 and 0.00448 at kappa = 0 and 0.9 (A = -0.5), i.e. the
-    (1 - kappa) law of Eq. (28)."""
+    """Sec. 3.2.2 (method 2, Fig. 3): sigma = 0.0459, 0.00448 and 0.000452 at kappa = 0, 0.9
+    and 0.99 (A = -0.5), each within 5%; the printed ratios sigma(kappa)/sigma(0) within 1%;
+    and sigma linear in (1 - kappa) (Eq. 28) within 3% at kappa = 0.5, 0.9 and 0.99."""
     g = GOLDEN["sigma_vs_kappa"]
-    s0 = _vdw_droplet_sigma(oracle_mod, -0.5, 0.0, ncpu)["sigma"]
-    s9 = _vdw_droplet_sigma(oracle_mod, -0.5, 0.9, ncpu)["sigma"]
-    assert abs(s0 / g["sigma"][0] - 1) < 0.05
-    assert abs(s9 / g["sigma"][1] - 1) < 0.05
-    assert abs((s9 / s0) / (1 - 0.9) - 1) < 0.03
-    # the paper's own printed ratio
-    assert abs((s9 / s0) / (g["sigma"][1] / g["sigma"][0]) - 1) < 0.01
+    kappas = (0.0, 0.5, 0.9, 0.99)
+    sig = {k: _vdw_droplet_sigma(oracle_mod, -0.5, k, ncpu)["sigma"] for k in kappas}
+    for k, want in zip(g["kappa"], g["sigma"]):
+        assert abs(sig[k] / want - 1) < 0.05, (k, sig[k], want)
+        if k > 0:
+            # the paper's own printed ratio
+            assert abs((sig[k] / sig[0.0]) / (want / g["sigma"][0]) - 1) < 0.01, k
+    for k in kappas[1:]:
+        assert abs((sig[k] / sig[0.0]) / (1 - k) - 1) < 0.03, (k, sig[k] / sig[0.0])
 
 
 def test_sigma_vs_A_method1(oracle_mod, ncpu):
