@@ -21,11 +21,13 @@ per update against the 78.6 TFLOP/s vector peak without packed math) and the
 bytes an unfused pair of single steps would have needed.  slab_share = the same
 kernel on one GPU's share of the lattice cut into 8 y-slabs (4096 x 512 rows
 plus 4 ghost rows per side), and the cost of refreshing the ghost rows.
-cpu_baseline = the FP64 CPU oracle on the host cores on a bounded sample of the
-same lattice.  end_to_end = wall times from initial field to results (a 100^2
-FP64 droplet on the GPU and, as a second CPU baseline, on the oracle, both from
-one initial field; the 200^2 Laplace sweep; the benchmark lattice with its host
-transfers).  These two legs are the only ones that run the oracle.
+cpu_baseline = the FP64 CPU oracle on every usable host core (count, quota and
+model recorded) on a bounded sample of the same lattice, and on the 100^2 FP64
+droplet end to end; it is the only leg that runs the oracle.  end_to_end = GPU
+wall times from initial field to results (the same droplet between the
+library's Maxwell densities; the 200^2 Laplace sweep; the benchmark lattice with
+its host transfers).  copy_ceiling = a plain device copy (the library's
+hand-written copy kernel and torch's), the practical HBM ceiling.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -48,14 +50,34 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 ALU_PEAK_TFLOPS = {"fp32": 78.6, "fp64": 78.6}
 FLOPS_PER_LU = 260  # FP arithmetic of one cell update in the single-step kernel's ISA
 # HBM bytes per launch of the two-step kernel in the default shape on 4096^2,
-# from rocprofv3 FETCH_SIZE + WRITE_SIZE (scaled by the copy calibration)
+# from rocprofv3 FETCH_SIZE + WRITE_SIZE (scaled by the copy calibration), and the
+# VALU issue utilisation of the same launches (SQ_INSTS_VALU against 256 CUs x
+# GRBM_GUI_ACTIVE / 8).  They hold for the kernel sources whose digest is
+# COUNTERS_SOURCE_DIGEST; for any other build they are reported as null.
 MEASURED_TRAFFIC = {("fp32", 256, 16): (788.7e6 + 619.2e6), ("fp64", 256, 69): (1356.0e6 + 1219.8e6)}
-# VALU issue utilisation of the same launches (SQ_INSTS_VALU against 256 CUs x GRBM_GUI_ACTIVE / 8)
 MEASURED_VALU_ISSUE = {("fp32", 256, 16): 0.796, ("fp64", 256, 69): 0.456}
+COUNTERS_SOURCE_DIGEST = "18dc45a84bf3af9b"
+KERNEL_SOURCES = ("lbm_device.h", "lbm_internal.h", "lbm_tile.h", "lbm_tile2.h", "lbm_step.hip")
 N = 4096
 RHO_MEAN = 0.183713  # (rho_v + rho_l)/2 of CS at 0.7Tc: (0.00929415 + 0.35813094)/2
 WORKLOAD = dict(nx=N, ny=N, eos="cs", T_over_Tc=0.7, A=-0.5, kappa=0.0)
+DROPLET_100 = dict(nx=100, ny=100, eos="cs", T_over_Tc=0.8, A=-0.5, kappa=0.0)
 BYTES_PER_LU = {"fp32": 72, "fp64": 144}
+
+
+def kernel_source_digest() -> str:
+    """sha256 (first 16 hex digits) of the step kernel's sources, in a fixed order."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1412_7228_amd", "csrc", name), "rb") as fh:
+            h.update(name.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
+def counters_current() -> bool:
+    return kernel_source_digest() == COUNTERS_SOURCE_DIGEST
 
 
 def parse():
@@ -76,24 +98,44 @@ def parse():
 
 
 def copy_bandwidth(mib, reps=10):
-    """A plain device copy of `mib` MiB (read + write) on torch's stream: GB/s moved."""
-    import torch
+    """The practical HBM ceiling: a device copy of `mib` MiB (read + write bytes / time),
+    by the library's hand-written copy kernel (lbm_copy_bytes: one 16-byte load and store
+    per lane) and by torch's copy, each timed with HIP events on torch's stream."""
+    import ctypes
 
+    import torch
+    from paper_1412_7228_amd import lbm
+
+    lib = lbm.load_library()
     n = mib * (1 << 20)
     src = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)
     dst = torch.empty_like(src)
-    dst.copy_(src)
-    torch.cuda.synchronize()
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    t0.record()
-    for _ in range(reps):
-        dst.copy_(src)
-    t1.record()
-    torch.cuda.synchronize()
-    ms = t0.elapsed_time(t1) / reps
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def own():
+        st = lib.lbm_copy_bytes(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()),
+                                ctypes.c_size_t(n), stream)
+        if st != 0:
+            raise RuntimeError(f"lbm_copy_bytes failed: {st}")
+
+    out = {}
+    for name, fn in (("hand_written", own), ("torch", lambda: dst.copy_(src))):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for _ in range(reps):
+            fn()
+        t1.record()
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1) / reps
+        out[name] = dict(ms=round(ms, 4), gbs=round(2 * n / (ms * 1e-3) / 1e9, 1))
+    ok = bool(torch.equal(dst, src))
     del src, dst
-    return dict(bytes_per_copy=2 * n, ms=ms, gbs=2 * n / (ms * 1e-3) / 1e9)
+    best = max(out.values(), key=lambda r: r["gbs"])["gbs"]
+    return dict(bytes_per_copy=2 * n, gbs=best, kernels=out, copy_correct=ok)
 
 
 def time_steps(lat, steps, warmup):
@@ -133,9 +175,14 @@ def gpu_measure(precision, steps, warmup, tile):
     gbs = BYTES_PER_LU[precision] * N * N / per_launch_s / 1e9
     tflops = FLOPS_PER_LU * N * N * spp / per_launch_s / 1e12
     tx, ty = lat.launch[0], lat.launch[1]
-    traffic = MEASURED_TRAFFIC.get((precision, tx, ty)) if spp == 2 else None
+    fresh = counters_current()
+    traffic = MEASURED_TRAFFIC.get((precision, tx, ty)) if (spp == 2 and fresh) else None
     roof = dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(gbs / HBM_PEAK_GBS, 4), traffic=traffic)
+                frac=round(gbs / HBM_PEAK_GBS, 4), traffic=traffic,
+                basis=f"launch minimum: the state read and written once per launch of {spp} steps, "
+                      f"{BYTES_PER_LU[precision] // spp} B per update")
+    roof["counters"] = dict(kernel_source_digest=kernel_source_digest(),
+                            taken_on_digest=COUNTERS_SOURCE_DIGEST, current=fresh)
     # bytes per lattice update, counted explicitly: the method's 72 B (FP32) / 144 B (FP64)
     # per update, the fused launch's minimum (the state in and out once for spp updates)
     # and what the counters measured
@@ -148,9 +195,14 @@ def gpu_measure(precision, steps, warmup, tile):
     if spp == 2:
         roof.update(unfused_equivalent_gbs=round(gbs * 2, 1),
                     frac_at_method_bytes=round(gbs * 2 / HBM_PEAK_GBS, 4),
+                    frac_at_method_bytes_note=(
+                        f"the method's {BYTES_PER_LU[precision]} B per update times the launch's "
+                        f"{spp} x N^2 updates over the launch time; above 1 because one launch "
+                        "advances two steps while reading and writing the state once (temporal "
+                        "blocking), so the per-update byte count stops being a ceiling"),
                     alu=dict(achieved=round(tflops, 2), peak=ALU_PEAK_TFLOPS[precision], unit="TFLOP/s",
                              frac=round(tflops / ALU_PEAK_TFLOPS[precision], 4),
-                             valu_issue_measured=MEASURED_VALU_ISSUE.get((precision, tx, ty))))
+                             valu_issue_measured=MEASURED_VALU_ISSUE.get((precision, tx, ty)) if fresh else None))
     res = dict(ms_per_step=ms / steps, mlups=lus / (ms * 1e-3) / 1e6, steps=steps,
                launch_ms=per_launch_s * 1e3, roofline=roof, tile=list(lat.launch), mass=ob["mass"],
                n_nonfinite=ob["n_nonfinite"])
@@ -229,20 +281,17 @@ def slab_share(launches=300, slabs=8, tiles=((0, 0), (256, 16), (256, 8), (128, 
 
 
 def end_to_end():
-    """Wall time of workloads from initial field to results: the 100^2 FP64
-    droplet (CS, 0.8Tc, R = 25, 5000 steps) on the GPU and on the oracle (all host cores),
-    and the 200^2 Laplace sweep (R 20..60, T/Tc 0.6..0.8, kappa 0..0.6 at A = -0.5, plus
-    the A = -0.9 rows at 0.6Tc; 60 drops, 20,000 FP32 steps) as one batch on the GPU, and
-    the benchmark lattice including its host transfers (the rate with PCIe in it)."""
+    """Wall time of workloads from initial field to results on the GPU, with nothing from
+    the oracle: the 100^2 FP64 droplet (CS, 0.8Tc, R = 25, 5000 steps) between the
+    library's Maxwell densities (lbm_coexistence), the 200^2 Laplace sweep (R 20..60,
+    T/Tc 0.6..0.8, kappa 0..0.6 at A = -0.5, plus the A = -0.9 rows at 0.6Tc; 60 drops,
+    20,000 FP32 steps) as one batch, and the benchmark lattice including its host
+    transfers (the rate with PCIe in it)."""
     import torch
-    import oracle
     from paper_1412_7228_amd import inputs, laplace, lbm
 
-    cfg = dict(nx=100, ny=100, eos="cs", T_over_Tc=0.8, A=-0.5, kappa=0.0, precision="fp64")
-    # one initial field for both sides, between the oracle's Maxwell densities
-    e = oracle.thermo.carnahan_starling()
-    _, Tc = oracle.thermo.critical_point(e)
-    rv, rl = oracle.thermo.maxwell(e, 0.8 * Tc)
+    cfg = dict(DROPLET_100, precision="fp64")
+    rv, rl = lbm.coexistence(cfg)
     rho = inputs.droplet(100, 100, 25.0, rl, rv, W=5.0, noise=1e-3, seed=0)
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -252,13 +301,6 @@ def end_to_end():
     ob_gpu = lat.observables()
     gpu_s = time.perf_counter() - t
     lat.close()
-    nthr = int(os.environ.get("OMP_NUM_THREADS") or min(16, os.cpu_count() or 1))
-    t = time.perf_counter()
-    o = oracle.Oracle(cfg, nthreads=nthr)
-    o.init_field(rho)
-    o.run(5000)
-    ob_orc = o.observables()
-    orc_s = time.perf_counter() - t
     # the benchmark lattice with its host transfers: initial density in (FP64, 134 MB),
     # 2000 steps, density field out (FP64)
     big = dict(WORKLOAD, precision="fp32")
@@ -279,8 +321,8 @@ def end_to_end():
     t = time.perf_counter()
     res = laplace.run_cases(cases, 20000, precision="fp32")
     sweep_s = time.perf_counter() - t
-    return dict(droplet_100_fp64_5000=dict(gpu_s=round(gpu_s, 3), oracle_s=round(orc_s, 3), oracle_threads=nthr,
-                                           sigma_gpu=ob_gpu["sigma"], sigma_oracle=ob_orc["sigma"]),
+    return dict(droplet_100_fp64_5000=dict(gpu_s=round(gpu_s, 3), sigma_gpu=ob_gpu["sigma"],
+                                           initial_densities="library (lbm_coexistence)"),
                 laplace_sweep_200_fp32_20000=dict(drops=len(cases), gpu_s=round(sweep_s, 3),
                                                  two_phase=int(sum(r["ok"] for r in res))),
                 lattice_4096_fp32_2000_with_host_io=dict(
@@ -289,13 +331,51 @@ def end_to_end():
                     rho_finite=bool(np.isfinite(out).all())))
 
 
+def host_cores() -> dict:
+    """The host's CPUs as this process sees them: nproc, the CPUs it may run on, the
+    cgroup CPU quota, the CPU model; `usable` = the threads the oracle runs on."""
+    info = dict(nproc=os.cpu_count() or 1)
+    try:
+        info["affinity"] = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        info["affinity"] = info["nproc"]
+    quota = None
+    try:
+        with open("/sys/fs/cgroup/cpu.max") as fh:
+            q, period = fh.read().split()[:2]
+            if q != "max":
+                quota = float(q) / float(period)
+    except (OSError, ValueError):
+        pass
+    info["cgroup_quota_cpus"] = quota
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    info["model"] = model
+    usable = info["affinity"]
+    if quota:
+        usable = max(1, min(usable, int(quota)))
+    info["usable"] = usable
+    info["omp_num_threads_env"] = os.environ.get("OMP_NUM_THREADS")
+    return info
+
+
 def cpu_baseline(seconds):
-    """The FP64 oracle (as it stands) on the full 4096^2 input, all host cores, as many
-    whole steps as fit in about `seconds`."""
+    """The FP64 oracle (as it stands) on the host cores: (1) the full 4096^2 input, as many
+    whole steps as fit in about `seconds`, on every usable core and on one thread; (2) the
+    100^2 FP64 droplet of end_to_end (5000 steps, from the oracle's own Maxwell densities)
+    end to end."""
     import oracle
     from paper_1412_7228_amd import inputs
 
-    nthr = int(os.environ.get("OMP_NUM_THREADS") or min(16, os.cpu_count() or 1))
+    host = host_cores()
+    nthr = host["usable"]
     o = oracle.Oracle(WORKLOAD, nthreads=nthr)
     o.init_field(inputs.spinodal(N, N, RHO_MEAN, noise=1e-2, seed=0))
     t = time.perf_counter()
@@ -309,10 +389,23 @@ def cpu_baseline(seconds):
     t = time.perf_counter()
     o.run(1)
     one_thread = N * N / (time.perf_counter() - t) / 1e6
+    del o
+    e = oracle.thermo.carnahan_starling()
+    _, Tc = oracle.thermo.critical_point(e)
+    rv, rl = oracle.thermo.maxwell(e, 0.8 * Tc)
+    rho = inputs.droplet(100, 100, 25.0, rl, rv, W=5.0, noise=1e-3, seed=0)
+    t = time.perf_counter()
+    d = oracle.Oracle(DROPLET_100, nthreads=nthr)
+    d.init_field(rho)
+    d.run(5000)
+    ob = d.observables()
+    e2e_s = time.perf_counter() - t
     return dict(value=N * N * k / dt / 1e6, unit="MLUPS", cores=nthr, kind="oracle",
                 sample=f"4096x4096 lattice (the benchmark's input), {k} FP64 steps after 1 untimed, "
                        f"{dt:.1f} s on {nthr} threads",
-                single_thread_mlups=round(one_thread, 2))
+                single_thread_mlups=round(one_thread, 2), host=host,
+                droplet_100_fp64_5000=dict(oracle_s=round(e2e_s, 3), sigma_oracle=ob["sigma"],
+                                           threads=nthr, initial_densities="oracle (thermo.maxwell)"))
 
 
 def main():
@@ -384,8 +477,14 @@ def main():
         "end_to_end": e2e,
         "cpu_baseline": cpu,
         "copy_ceiling": None if copy is None else {
-            "gbs": round(copy["gbs"], 1), "bytes": copy["bytes_per_copy"],
-            "note": "device-to-device copy of the same stream, read + write bytes / time"},
+            "gbs": copy["gbs"], "bytes": copy["bytes_per_copy"], "kernels": copy["kernels"],
+            "copy_correct": copy["copy_correct"],
+            "frac_of_peak": round(copy["gbs"] / HBM_PEAK_GBS, 4),
+            "step_traffic_frac_of_copy": (round(r32["roofline"]["traffic_gbs"] / copy["gbs"], 4)
+                                          if r32["roofline"].get("traffic_gbs") else None),
+            "step_minimum_frac_of_copy": round(r32["roofline"]["achieved"] / copy["gbs"], 4),
+            "note": "device-to-device copy, read + write bytes / time; the best of the library's "
+                    "hand-written copy kernel and torch's copy"},
     }
     print(json.dumps(line), flush=True)
 

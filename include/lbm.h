@@ -389,6 +389,15 @@ lbm_status lbm_mlp_set_data(lbm_mlp* m, const float* x, const float* t, int32_t 
  * may be NULL) receives the loss before each step. */
 lbm_status lbm_mlp_train(lbm_mlp* m, int32_t iters, float lr, float* loss_out);
 
+/* Measurement helper (not part of the method): copies `bytes` bytes from src
+ * to dst, both device pointers, 16-byte aligned, bytes a multiple of 16, with
+ * one plain copy kernel (one 16-byte load and store per lane), enqueued on
+ * hip_stream (NULL: the null stream), asynchronous.  Its bandwidth is the
+ * practical HBM ceiling that the step kernels' rooflines are read against.
+ * LBM_EINVAL for NULL, misaligned or ragged arguments; LBM_EDEVICE if the
+ * launch fails.  The buffers stay owned by the caller and must not overlap. */
+lbm_status lbm_copy_bytes(void* dst, const void* src, size_t bytes, void* hip_stream);
+
 const char* lbm_strerror(lbm_status s);
 /* Message of the last error on the calling thread ("" if none). */
 const char* lbm_last_error(void);

@@ -14,12 +14,14 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm.so")
-SOURCES = ["lbm_step.hip", "lbm_fields.hip", "lbm_batch.hip", "lbm_mlp.hip", "lbm_api.hip"]
+SOURCES = ["lbm_step.hip", "lbm_fields.hip", "lbm_batch.hip", "lbm_mlp.hip", "lbm_api.hip", "lbm_copy.hip"]
+OBJDIR = os.path.join(ROOT, "_build")
 ARCH = os.environ.get("LBM_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
@@ -43,16 +45,27 @@ def hipcc() -> str:
     return "hipcc"
 
 
-def build(verbose: bool = False) -> str:
-    """Always recompiles; returns the path of the shared library."""
-    tmp = LIB + ".tmp"
-    cmd = [hipcc()] + FLAGS + [os.path.join(CSRC, s) for s in SOURCES] + ["-o", tmp]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError(f"hipcc failed with status {res.returncode}")
+        raise RuntimeError(f"hipcc failed with status {res.returncode}: {' '.join(cmd)}")
+
+
+def build(verbose: bool = False, jobs: int | None = None) -> str:
+    """Always recompiles (each source to an object in parallel, then one link);
+    returns the path of the shared library."""
+    os.makedirs(OBJDIR, exist_ok=True)
+    compile_flags = [f for f in FLAGS if f != "-shared"]
+    objs = [os.path.join(OBJDIR, os.path.splitext(s)[0] + ".o") for s in SOURCES]
+    cmds = [[hipcc()] + compile_flags + ["-c", os.path.join(CSRC, s), "-o", o] for s, o in zip(SOURCES, objs)]
+    jobs = jobs or min(len(cmds), max(1, os.cpu_count() or 1), 16)
+    with ThreadPoolExecutor(jobs) as pool:
+        list(pool.map(lambda c: _run(c, verbose), cmds))
+    tmp = LIB + ".tmp"
+    _run([hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC"] + objs + ["-o", tmp], verbose)
     os.replace(tmp, LIB)
     return LIB
 
