@@ -8,7 +8,11 @@ with two fused steps per launch, with HIP events on the batch's stream, and
 prints one JSON line: MLUPS over all domains, the launch shapes, and how many
 domains stayed two-phase.
 
-    python -m paper_1412_7228_amd.batchbench [--steps 20000] [--domains 256]
+Draws that the method cannot hold (laplace.feasible_batch_draws: a flat slab of
+the draw's parameters faults, collapses or loses its second phase) are redrawn
+from the same seeded stream, and the redraws are reported.
+
+    python -m paper_1412_7228_amd.batchbench [--steps 20000] [--domains 256] [--no-screen]
 """
 from __future__ import annotations
 
@@ -21,16 +25,23 @@ import numpy as np
 from . import autotune, inputs, laplace, lbm
 
 
-def build(domains: int, seed: int, precision: str = "fp32"):
-    draws = inputs.batch_draws(domains, seed)
+def build(domains: int, seed: int, precision: str = "fp32", screen: bool = True,
+          max_ratio: float | None = None):
+    """The batch of `domains` droplets from the seeded draw stream: the first feasible
+    draws (laplace.feasible_batch_draws) unless screen is False.  Returns (batch, cases,
+    cells, screen report)."""
+    if screen:
+        draws, report = laplace.feasible_batch_draws(domains, seed, max_ratio=max_ratio)
+    else:
+        draws, report = inputs.batch_draws(domains, seed), None
     cases = [dict(n=d["nx"], R=d["R"], T_over_Tc=d["T_over_Tc"], A=d["A"], kappa=d["kappa"],
-                  seed=d["seed"]) for d in draws]
+                  seed=d["seed"], screen_ratio=d.get("screen_ratio")) for d in draws]
     cfgs = [laplace.case_config(c, precision) for c in cases]
     b = lbm.Batch(cfgs)
     for i, (c, cfg) in enumerate(zip(cases, cfgs)):
         b.init_field(i, laplace.initial_density(c, cfg))
     cells = sum(c["n"] * c["n"] for c in cases)
-    return b, cases, cells
+    return b, cases, cells, report
 
 
 def time_mode(b, mode, tile, steps, steps_per_pass=1):
@@ -54,17 +65,24 @@ def main():
     ap.add_argument("--domains", type=int, default=256)
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--tune", action="store_true", help="run the autotuner first")
+    ap.add_argument("--no-screen", action="store_true", help="keep infeasible draws (no redraw)")
+    ap.add_argument("--max-ratio", type=float, default=laplace.SCREEN_MAX_RATIO,
+                    help="screen: largest flat density ratio kept (0: no cap)")
+    ap.add_argument("--modes", default="1,2x128,2x256", help="launch modes to time")
     a = ap.parse_args()
     t0 = time.time()
-    b, cases, cells = build(a.domains, a.seed)
-    print(f"[batch] {a.domains} domains, {cells} cells, setup {time.time() - t0:.1f} s", flush=True)
+    b, cases, cells, report = build(a.domains, a.seed, screen=not a.no_screen, max_ratio=a.max_ratio or None)
+    redraws = None if report is None else report["redraws"]
+    print(f"[batch] {a.domains} domains, {cells} cells, {redraws} redraws, setup {time.time() - t0:.1f} s",
+          flush=True)
     tuned = None
     if a.tune:
         tuned = autotune.tune_batch(b, steps=20, use_cache=False)
         print(f"[batch] autotune {tuned}", flush=True)
     res = {}
-    for mode, tile, spp in (("per_step", (64, 16), 1), ("per_step", (128, 16), 2),
-                            ("per_step", (256, 16), 2)):
+    all_modes = {"1": ("per_step", (64, 16), 1), "2x128": ("per_step", (128, 16), 2),
+                 "2x256": ("per_step", (256, 16), 2)}
+    for mode, tile, spp in (all_modes[m] for m in a.modes.split(",")):
         ms = time_mode(b, mode, tile, a.steps, spp)
         key = f"{mode}{'2' if spp == 2 else ''}_{tile[0]}x{tile[1]}"
         res[key] = dict(ms=ms, mlups=cells * a.steps / (ms * 1e-3) / 1e6, tile=list(tile),
@@ -72,9 +90,18 @@ def main():
         print(f"[batch] {key} {res[key]}", flush=True)
     obs = b.observables()
     ok = sum(1 for c, o in zip(cases, obs) if o["n_nonfinite"] == 0 and o["rho_in"] > 1.5 * o["rho_out"] > 0)
+    faulted = [dict(domain=i, side=c["n"], R=round(c["R"], 2), T_over_Tc=round(c["T_over_Tc"], 4),
+                    A=round(c["A"], 4), kappa=round(c["kappa"], 4), screen_ratio=c.get("screen_ratio"))
+               for i, (c, o) in enumerate(zip(cases, obs)) if o["n_nonfinite"] > 0 or o["n_domain"] > 0]
+    faults = len(faulted)
     line = dict(metric="MLUPS of the uneven droplet batch (FP32)", domains=a.domains, cells=cells,
-                timed_steps_per_mode=a.steps, total_steps=3 * (a.steps + 10), modes=res,
-                two_phase_domains=ok,
+                timed_steps_per_mode=a.steps, total_steps=len(res) * (a.steps + 10), modes=res,
+                two_phase_domains=ok, domains_with_faults=faults, faulted=faulted,
+                max_screen_ratio=max((c.get("screen_ratio") or 0) for c in cases),
+                largest_screen_ratios=sorted(((c.get("screen_ratio") or 0) for c in cases), reverse=True)[:8],
+                feasibility=None if report is None else dict(redraws=report["redraws"],
+                                                             screen_steps=report["screen_steps"],
+                                                             rejected=report["rejected"]),
                 autotune=tuned, seconds=time.time() - t0)
     print(json.dumps(line), flush=True)
 

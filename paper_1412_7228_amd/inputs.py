@@ -14,8 +14,10 @@ Sec. 4.1):
 * ``slab``     -- a flat liquid layer (two straight interfaces), same profile;
 * ``spinodal`` -- a uniform mean density times (1 + noise * xi);
 * ``taylor_green`` -- the decaying Taylor-Green vortex velocity field;
-* ``batch_draws`` -- the uneven batch of Laplace droplets: integer side
-  U{lo..hi}, R = u * side with u ~ U[r_lo, r_hi], T/Tc ~ U, kappa ~ U, A ~ U.
+* ``batch_draw_stream`` / ``batch_draws`` -- the uneven batch of Laplace
+  droplets: integer side U{lo..hi}, R = u * side with u ~ U[r_lo, r_hi],
+  T/Tc ~ U, kappa ~ U, A ~ U (the feasibility screen that redraws from the
+  stream runs the method, so it lives with the runs, in ``laplace``).
 
 All generators use numpy's PCG64 seeded with the given seed.
 """
@@ -82,17 +84,25 @@ def taylor_green(n: int, u0: float = 0.01, rho0: float = 1.0, modes: int = 1):
     return np.full((n, n), rho0), ux, uy
 
 
+def batch_draw_stream(seed: int, side=(64, 512), r_frac=(0.15, 0.35), t_over_tc=(0.6, 0.85),
+                      kappa=(0.0, 0.8), A=(-0.7, -0.3)):
+    """Endless seeded stream of independent draws of the uneven droplet batch, one dict per
+    domain (``index`` counts the draws of the stream)."""
+    g = rng(seed)
+    i = 0
+    while True:
+        s = int(g.integers(side[0], side[1] + 1))
+        yield dict(index=i, nx=s, ny=s,
+                   R=float(g.uniform(*r_frac) * s),
+                   T_over_Tc=float(g.uniform(*t_over_tc)),
+                   kappa=float(g.uniform(*kappa)),
+                   A=float(g.uniform(*A)),
+                   seed=int(g.integers(0, 2**31 - 1)))
+        i += 1
+
+
 def batch_draws(n: int, seed: int, side=(64, 512), r_frac=(0.15, 0.35), t_over_tc=(0.6, 0.85),
                 kappa=(0.0, 0.8), A=(-0.7, -0.3)) -> list[dict]:
-    """Independent draws of the uneven droplet batch, one dict per domain."""
-    g = rng(seed)
-    out = []
-    for i in range(n):
-        s = int(g.integers(side[0], side[1] + 1))
-        out.append(dict(index=i, nx=s, ny=s,
-                        R=float(g.uniform(*r_frac) * s),
-                        T_over_Tc=float(g.uniform(*t_over_tc)),
-                        kappa=float(g.uniform(*kappa)),
-                        A=float(g.uniform(*A)),
-                        seed=int(g.integers(0, 2**31 - 1))))
-    return out
+    """The first n draws of :func:`batch_draw_stream` (no feasibility screen)."""
+    stream = batch_draw_stream(seed, side, r_frac, t_over_tc, kappa, A)
+    return [next(stream) for _ in range(n)]

@@ -12,8 +12,17 @@ least-squares slope of dp against 1/R_e through the origin.
 Everything numerical runs in the library's kernels; this module only builds
 initial fields (tanh droplets between the Maxwell densities that the library
 computes on the host) and collects results.
+
+The uneven batch's parameter ranges reach temperatures below the lowest one at
+which the model holds two phases for its A (Sec. 3.1.2: the gas branch
+collapses).  :func:`feasible_batch_draws` screens every draw with the method
+itself: its (T/Tc, A, kappa) run on a thin flat slab, the one-dimensional
+coexistence problem of Table 1, and a draw that faults, collapses or loses its
+second phase there is redrawn from the same seeded stream.
 """
 from __future__ import annotations
+
+import itertools
 
 import numpy as np
 
@@ -85,3 +94,76 @@ def sweep_cases(radii=(20, 30, 40, 50, 60), temps=(0.6, 0.7, 0.8), kappas=(0.0, 
                 for R in radii:
                     cases.append(dict(n=n, R=R, T_over_Tc=T, A=a2, kappa=k, seed=len(cases)))
     return cases
+
+
+SCREEN_SLAB = (64, 4)      # flat slab: 64 cells across two interfaces, 4 rows
+SCREEN_STEPS = 20000
+SCREEN_MIN_RATIO = 2.0     # rho_max / rho_min that still counts as two phases
+# largest flat density ratio kept: draws whose gas sinks towards zero (ratios of 10^4
+# and more after the screen) hold on the slab for a while but fault as droplets
+SCREEN_MAX_RATIO = 1000.0
+
+
+def screen_flat(cases: list, steps: int = SCREEN_STEPS, precision: str = "fp32",
+                max_ratio: float | None = None) -> list:
+    """Runs each case's (T/Tc, A, kappa, EOS) on a thin periodic flat slab (a liquid layer
+    between the library's Maxwell densities) on the batched engine for `steps` steps.
+    Returns one dict per case: ``ok`` (finite, positive, no U > 0 cell, rho_max / rho_min
+    >= SCREEN_MIN_RATIO), the slab's liquid and gas densities and their ratio, and the
+    reason when not ok."""
+    nx, ny = SCREEN_SLAB
+    cfgs = []
+    for c in cases:
+        cfg = dict(nx=nx, ny=ny, eos=c.get("eos", "cs"), T_over_Tc=float(c["T_over_Tc"]),
+                   A=float(c["A"]), kappa=float(c["kappa"]), precision=precision)
+        if "K" in c:
+            cfg["K"] = float(c["K"])
+        cfgs.append(cfg)
+    b = lbm.Batch(cfgs)
+    b.set_launch("per_step", 128, 16, steps_per_pass=2)
+    for i, cfg in enumerate(cfgs):
+        rv, rl = lbm.coexistence(cfg)
+        b.init_field(i, inputs.slab(nx, ny, rl, rv, W=5.0))
+    b.step(steps)
+    obs = b.observables()
+    b.close()
+    out = []
+    for o in obs:
+        lo, hi = o["rho_min"], o["rho_max"]
+        reason = None
+        if o["n_nonfinite"] > 0 or not (np.isfinite(lo) and np.isfinite(hi)):
+            reason = "non-finite or non-positive density"
+        elif o["n_domain"] > 0:
+            reason = "U > 0"
+        elif not lo > 0.0:
+            reason = "gas density not positive"
+        elif hi < SCREEN_MIN_RATIO * lo:
+            reason = "one phase left"
+        elif max_ratio is not None and hi > max_ratio * lo:
+            reason = f"density ratio above {max_ratio:g}"
+        out.append(dict(ok=reason is None, rho_l=hi, rho_v=lo, ratio=(hi / lo) if lo > 0 else None,
+                        reason=reason))
+    return out
+
+
+def feasible_batch_draws(n: int, seed: int, steps: int = SCREEN_STEPS,
+                         max_ratio: float | None = SCREEN_MAX_RATIO, **ranges) -> tuple:
+    """The first n draws of the seeded stream (inputs.batch_draw_stream) that pass
+    :func:`screen_flat` with a density ratio of at most max_ratio, in stream order; returns
+    (draws, report) with the number of draws rejected before the n-th kept one and each
+    rejected draw's parameters and reason.  Each kept draw carries its slab's ratio."""
+    stream = inputs.batch_draw_stream(seed, **ranges)
+    kept, rejected = [], []
+    while len(kept) < n:
+        need = n - len(kept)
+        cand = list(itertools.islice(stream, max(16, need + need // 4)))
+        for d, r in zip(cand, screen_flat(cand, steps, max_ratio=max_ratio)):
+            if len(kept) == n:
+                break
+            if r["ok"]:
+                kept.append(dict(d, screen_ratio=r["ratio"]))
+            else:
+                rejected.append(dict(index=d["index"], T_over_Tc=d["T_over_Tc"], A=d["A"],
+                                     kappa=d["kappa"], ratio=r["ratio"], reason=r["reason"]))
+    return kept, dict(kept=len(kept), redraws=len(rejected), rejected=rejected, screen_steps=steps,
+                      screen_slab=list(SCREEN_SLAB), max_ratio=max_ratio)

@@ -258,16 +258,23 @@ def test_one_graph_per_call_replayed(lbm):
 
 
 def test_full_size_uneven_batch_sampled_domains(lbm, oracle_mod):
-    """The uneven batch at full size (256 droplets, sides 64-512, 24.3 M cells, FP32) in
+    """The uneven batch at full size (256 droplets, sides 64-512, about 25 M cells, FP32) in
     the library's default batch launch (two steps per launch, 256 x 16 tiles, one graph
-    per call), 201 steps (100 two-step launches and a single step).  The draws reach
-    T/Tc = 0.6, below the lowest temperature at which the method stays stable for these
-    A (about 0.69 Tc at A = -0.5, Sec. 3.1.2), so some drops fail (each reported through
-    its own domain's observables); every domain without a fault keeps its mass,
-    five sampled domains (the smallest, the largest and three drawn) are bitwise the
-    same lattice run alone, and the smallest domain without a fault matches the FP64
-    oracle.  Densities start from the oracle's Maxwell construction for each draw."""
-    draws = inputs.batch_draws(256, 3)
+    per call), 201 steps (100 two-step launches and a single step).  The draws are the
+    first 256 of the seeded stream that pass the feasibility screen (draws below the
+    lowest temperature at which the method holds two phases for their A, Sec. 3.1.2, are
+    redrawn), so no domain may fault; every domain keeps its mass, five sampled domains
+    (the smallest, the largest and three drawn) are bitwise the same lattice run alone,
+    and the smallest domain matches the FP64 oracle.  Densities start from the oracle's
+    Maxwell construction for each draw."""
+    from paper_1412_7228_amd import laplace
+
+    say("uneven batch: feasibility screen of the draw stream")
+    draws, report = laplace.feasible_batch_draws(256, 3)
+    say(f"  {report['redraws']} redraws: " + ", ".join(
+        f"T/Tc {r['T_over_Tc']:.3f} A {r['A']:.3f} ({r['reason']})" for r in report["rejected"]))
+    assert len(draws) == 256 and report["redraws"] > 0
+    assert all(r["T_over_Tc"] < 0.72 for r in report["rejected"])
     say("uneven batch, 256 domains, 201 steps")
     e = th.carnahan_starling()
     _, Tc = th.critical_point(e)
@@ -291,12 +298,9 @@ def test_full_size_uneven_batch_sampled_domains(lbm, oracle_mod):
     obs = b.observables()
     assert all(o["step"] == steps for o in obs)
     ok = [i for i, o in enumerate(obs) if o["n_nonfinite"] == 0 and o["n_domain"] == 0]
-    say(f"  {len(ok)} of 256 domains without a fault after {steps} steps; failed at T/Tc "
-        f"{sorted(round(cfgs[i]['T_over_Tc'], 3) for i in range(256) if i not in ok)}")
-    assert len(ok) > 128
-    # Sec. 3.1.2: stable down to 0.69 Tc at A = -0.5 and 0.79 Tc at A = +0.5, so for the
-    # draws' A <= -0.3 a drop at 0.72 Tc or above must not fail
-    assert all(cfgs[i]["T_over_Tc"] < 0.72 for i in range(256) if i not in ok)
+    say(f"  {len(ok)} of 256 domains without a fault after {steps} steps; failed at (T/Tc, A) "
+        f"{sorted((round(cfgs[i]['T_over_Tc'], 3), round(cfgs[i]['A'], 3)) for i in range(256) if i not in ok)}")
+    assert len(ok) == 256
     m1 = np.array([obs[i]["mass"] for i in ok])
     assert np.abs(m1 / m0[ok] - 1).max() < 1e-6
     sides = [c["nx"] for c in cfgs]
@@ -318,3 +322,30 @@ def test_full_size_uneven_batch_sampled_domains(lbm, oracle_mod):
     got = b.field(small, "rho")
     assert float(np.abs(got - want).max() / np.abs(want).max()) < 1e-5
     b.close()
+
+
+# (A, T/Tc, feasible): the oracle's exact discrete flat-interface balance (N = 64) has a
+# positive gas density at the first three points and only negative ones at the last two
+SCREEN_POINTS = [(-0.5, 0.80, True), (-0.5, 0.70, True), (-0.7, 0.60, True),
+                 (-0.3, 0.65, False), (-0.3, 0.60, False)]
+
+
+def test_feasibility_screen_agrees_with_the_flat_balance(lbm):
+    """The product-code feasibility screen (a flat slab of the draw's parameters run on the
+    batched engine) accepts exactly the points where the oracle's exact steady flat balance
+    has a positive gas density (Sec. 3.1.2: A bounds the lowest temperature), and its
+    slab densities are the balance's (rho_l within 0.5%, rho_v within 5%)."""
+    from paper_1412_7228_amd import laplace
+
+    say("feasibility screen against the discrete flat balance")
+    e = th.carnahan_starling()
+    _, Tc = th.critical_point(e)
+    cases = [dict(T_over_Tc=T, A=A, kappa=0.3) for A, T, _ in SCREEN_POINTS]
+    res = laplace.screen_flat(cases)
+    for (A, T, feasible), r in zip(SCREEN_POINTS, res):
+        _, rv, rl = th.discrete_flat_balance(e, T * Tc, A, N=laplace.SCREEN_SLAB[0])
+        say(f"  A={A} T/Tc={T}: screen {r}, balance rho_v={rv:.6g} rho_l={rl:.6g}")
+        assert (rv > 0) == feasible
+        assert r["ok"] == feasible, (A, T, r)
+        if feasible:
+            assert abs(r["rho_l"] / rl - 1) < 5e-3 and abs(r["rho_v"] / rv - 1) < 0.05

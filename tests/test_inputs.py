@@ -49,3 +49,15 @@ def test_batch_draws_in_range_and_seeded():
         assert 0.6 <= x["T_over_Tc"] <= 0.85 and 0.0 <= x["kappa"] <= 0.8 and -0.7 <= x["A"] <= -0.3
     sides = np.array([x["nx"] for x in d])
     assert sides.min() < 100 and sides.max() > 450  # spans the range
+
+
+def test_batch_draws_are_the_head_of_the_seeded_stream():
+    """The redraw of infeasible draws continues the same seeded stream: batch_draws(n) is
+    its first n draws, and draws are numbered along it."""
+    import itertools
+
+    d = inputs.batch_draws(40, 3)
+    s = list(itertools.islice(inputs.batch_draw_stream(3), 60))
+    assert d == s[:40]
+    assert [x["index"] for x in s] == list(range(60))
+    assert s[40:] != list(itertools.islice(inputs.batch_draw_stream(4), 40, 60))
