@@ -1,0 +1,119 @@
+"""Writes ``laplace_sweep_200.json``: the FP64 oracle's observables of every drop of the
+200 x 200 Carnahan-Starling Laplace sweep (Eq. 22; the droplet test of Sec. 3.1.1 and
+Sec. 4.1 on the workload's lattice): R in {20, 30, 40, 50, 60}, T/Tc in {0.6, 0.7, 0.8},
+kappa in {0, 0.3, 0.6} at A = -0.5, and the A = -0.9 rows at T/Tc = 0.6 (60 drops),
+each observed after 5,000, 10,000, 15,000 and 20,000 steps.
+
+Only ``oracle/`` computes here.  Initial fields come from the seeded generator
+``paper_1412_7228_amd.inputs.droplet`` (no lattice Boltzmann arithmetic in it) between
+the oracle's Maxwell densities, which are stored with each case so that a test rebuilds
+the same field bit for bit.  Drops run in parallel worker processes, one oracle thread
+each (the oracle's result does not depend on its thread count).
+
+    python tests/golden/make_laplace_sweep.py [--workers 8] [--out tests/golden/laplace_sweep_200.json]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+from multiprocessing import Pool
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+N = 200
+RADII = (20, 30, 40, 50, 60)
+TEMPS = (0.6, 0.7, 0.8)
+KAPPAS = (0.0, 0.3, 0.6)
+A_MAIN = -0.5
+A_EXTRA, TEMPS_EXTRA = -0.9, (0.6,)
+CHECKPOINTS = (5000, 10000, 15000, 20000)
+W, NOISE = 5.0, 1e-3
+OBS_KEYS = ("mass", "mom_x", "mom_y", "rho_min", "rho_max", "rho_in", "rho_out", "p_in", "p_out",
+            "dp", "R_e", "sigma", "max_u", "n_domain", "n_nonfinite")
+
+
+def sweep_cases() -> list:
+    """The 60 drops in a fixed order; seed = position in the list."""
+    cases = []
+    for A, temps in ((A_MAIN, TEMPS), (A_EXTRA, TEMPS_EXTRA)):
+        for T in temps:
+            for k in KAPPAS:
+                for R in RADII:
+                    cases.append(dict(n=N, R=float(R), T_over_Tc=T, A=A, kappa=k, seed=len(cases),
+                                      W=W, noise=NOISE))
+    return cases
+
+
+def field_digest(rho) -> str:
+    import numpy as np
+
+    return hashlib.sha256(np.ascontiguousarray(rho, dtype=np.float64).tobytes()).hexdigest()[:16]
+
+
+def run_case(case: dict) -> dict:
+    import numpy as np
+
+    import oracle
+    from oracle import thermo as th
+    from paper_1412_7228_amd import inputs
+
+    e = th.carnahan_starling()
+    _, Tc = th.critical_point(e)
+    rv, rl = th.maxwell(e, case["T_over_Tc"] * Tc)
+    rho0 = inputs.droplet(N, N, case["R"], rl, rv, W=case["W"], noise=case["noise"], seed=case["seed"])
+    cfg = dict(nx=N, ny=N, eos="cs", T_over_Tc=case["T_over_Tc"], A=case["A"], kappa=case["kappa"])
+    o = oracle.Oracle(cfg, nthreads=1)
+    o.init_field(rho0)
+    obs, done = {}, 0
+    t0 = time.time()
+    for s in CHECKPOINTS:
+        o.run(s - done)
+        done = s
+        ob = o.observables()
+        obs[str(s)] = {k: (float(ob[k]) if np.isfinite(ob[k]) else None) for k in OBS_KEYS}
+    return dict(case=case, rho_v0=rv, rho_l0=rl, rho0_sha256_16=field_digest(rho0),
+                oracle_seconds=round(time.time() - t0, 1), observables=obs)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workers", type=int, default=os.cpu_count() or 1)
+    ap.add_argument("--out", default=os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                                  "laplace_sweep_200.json"))
+    ap.add_argument("--limit", type=int, default=0, help="first n cases only (a quick check)")
+    args = ap.parse_args()
+    import oracle
+
+    oracle.build(force=False)
+    cases = sweep_cases()
+    if args.limit:
+        cases = cases[: args.limit]
+    t0 = time.time()
+    with Pool(args.workers) as pool:
+        results = []
+        for r in pool.imap(run_case, cases):
+            results.append(r)
+            c = r["case"]
+            o = r["observables"][str(CHECKPOINTS[-1])]
+            print(f"[{len(results)}/{len(cases)}] A={c['A']} T={c['T_over_Tc']} kappa={c['kappa']} "
+                  f"R={c['R']}: sigma={o['sigma']} rho_in={o['rho_in']} rho_out={o['rho_out']} "
+                  f"({r['oracle_seconds']} s)", flush=True)
+    doc = dict(
+        source="FP64 oracle (oracle/lbm_oracle.c), written by tests/golden/make_laplace_sweep.py",
+        workload="200 x 200 periodic CS droplets (a=1, b=4, R=1, K=1), tanh profile of width 5 "
+                 "between the Maxwell densities, times (1 + 1e-3 xi), xi ~ U[-1, 1) seeded per drop",
+        rates=dict(s_e=1.0, s_eps=1.0, s_q=8.0 / 7.0, s_nu=1.0, G=-1.0),
+        checkpoints=list(CHECKPOINTS), wall_seconds=round(time.time() - t0, 1), cases=results)
+    with open(args.out, "w") as fh:
+        json.dump(doc, fh, indent=1)
+    print(f"wrote {args.out} ({len(results)} drops, {time.time() - t0:.0f} s)")
+
+
+if __name__ == "__main__":
+    main()
