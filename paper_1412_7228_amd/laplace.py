@@ -153,10 +153,11 @@ def feasible_batch_draws(n: int, seed: int, steps: int = SCREEN_STEPS,
     (draws, report) with the number of draws rejected before the n-th kept one and each
     rejected draw's parameters and reason.  Each kept draw carries its slab's ratio."""
     stream = inputs.batch_draw_stream(seed, **ranges)
-    kept, rejected = [], []
+    kept, rejected, screened = [], [], 0
     while len(kept) < n:
         need = n - len(kept)
         cand = list(itertools.islice(stream, max(16, need + need // 4)))
+        screened += len(cand)
         for d, r in zip(cand, screen_flat(cand, steps, max_ratio=max_ratio)):
             if len(kept) == n:
                 break
@@ -166,4 +167,4 @@ def feasible_batch_draws(n: int, seed: int, steps: int = SCREEN_STEPS,
                 rejected.append(dict(index=d["index"], T_over_Tc=d["T_over_Tc"], A=d["A"],
                                      kappa=d["kappa"], ratio=r["ratio"], reason=r["reason"]))
     return kept, dict(kept=len(kept), redraws=len(rejected), rejected=rejected, screen_steps=steps,
-                      screen_slab=list(SCREEN_SLAB), max_ratio=max_ratio)
+                      screen_slab=list(SCREEN_SLAB), max_ratio=max_ratio, screened=screened)

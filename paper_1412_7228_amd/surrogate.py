@@ -142,17 +142,31 @@ class Surrogate:
 # ---------------------------------------------------------------------------
 # The study
 # ---------------------------------------------------------------------------
+def _count(cost: dict, screen_report: dict, draws: list, steps: int):
+    """Adds one training batch to the run accounting: its droplet runs and lattice updates,
+    and the feasibility screen's slab runs and updates."""
+    cost["runs"] += len(draws)
+    cost["updates"] += sum(d["nx"] * d["ny"] for d in draws) * steps
+    sx, sy = screen_report["screen_slab"]
+    cost["screen_runs"] += screen_report["screened"]
+    cost["screen_updates"] += screen_report["screened"] * sx * sy * screen_report["screen_steps"]
+    cost["redraws"] += screen_report["redraws"]
+
+
 def training_set(n_batches: int, seed: int, steps: int, side=(64, 512), domains: int = 256,
                  r_range=(20.0, 60.0), log=print):
-    """Droplets drawn as in the uneven batch (side, R = u * side, T/Tc, kappa, A),
-    run in batches of `domains`; returns X [n, 3], Y [n, 3] of the runs that stayed
-    two-phase with an equimolar radius in `r_range`, the count of draws outside the
-    model's range, and the count left out for their radius.  sigma = dp * R_e of
+    """Droplets drawn as in the uneven batch (side, R = u * side, T/Tc, kappa, A; the
+    feasible draws of each seeded stream), run in batches of `domains`; returns X [n, 3],
+    Y [n, 3] of the runs that stayed two-phase with an equimolar radius in `r_range`, the
+    count of runs outside the model's range, the count left out for their radius, and
+    the run accounting (droplet runs, lattice updates, screen runs).  sigma = dp * R_e of
     one drop depends on the drop's size (lattice effects below R ~ 20, slow
     relaxation above R ~ 60), which three inputs cannot see."""
     X, Y, bad, sized = [], [], 0, 0
+    cost = dict(runs=0, updates=0, screen_runs=0, screen_updates=0, redraws=0)
     for bi in range(n_batches):
-        draws = inputs.batch_draws(domains, seed + bi, side=side)
+        draws, rep = laplace.feasible_batch_draws(domains, seed + bi, side=side)
+        _count(cost, rep, draws, steps)
         cases = [dict(n=d["nx"], R=d["R"], T_over_Tc=d["T_over_Tc"], A=d["A"], kappa=d["kappa"],
                       seed=d["seed"]) for d in draws]
         t0 = time.time()
@@ -168,17 +182,20 @@ def training_set(n_batches: int, seed: int, steps: int, side=(64, 512), domains:
                 Y.append((r["sigma"], r["rho_in"], r["rho_out"]))
         log(f"[surrogate] training batch {bi}: {sum(r['ok'] for r in res)}/{len(res)} two-phase, "
             f"{time.time() - t0:.1f} s")
-    return np.array(X), np.array(Y), bad, sized
+    return np.array(X), np.array(Y), bad, sized, cost
 
 
 def training_set_fixed(n_batches: int, seed: int, steps: int, n: int = 200, R: float = 40.0,
                        domains: int = 256, log=print):
     """Droplets of one geometry (n x n lattice, initial radius R) with (T/Tc, kappa, A)
-    drawn from the uneven batch's ranges, run in batches of `domains`; returns X, Y
-    of the runs that stayed two-phase and the count that did not."""
+    drawn from the uneven batch's ranges (feasible draws), run in batches of `domains`;
+    returns X, Y of the runs that stayed two-phase, the count that did not, and the run
+    accounting."""
     X, Y, bad = [], [], 0
+    cost = dict(runs=0, updates=0, screen_runs=0, screen_updates=0, redraws=0)
     for bi in range(n_batches):
-        draws = inputs.batch_draws(domains, seed + bi, side=(n, n))
+        draws, rep = laplace.feasible_batch_draws(domains, seed + bi, side=(n, n))
+        _count(cost, rep, [dict(d, nx=n, ny=n) for d in draws], steps)
         cases = [dict(n=n, R=R, T_over_Tc=d["T_over_Tc"], A=d["A"], kappa=d["kappa"], seed=d["seed"])
                  for d in draws]
         t0 = time.time()
@@ -192,7 +209,7 @@ def training_set_fixed(n_batches: int, seed: int, steps: int, n: int = 200, R: f
                 Y.append((r["sigma"], r["rho_in"], r["rho_out"]))
         log(f"[surrogate] training batch {bi} ({n}^2, R = {R:g}): "
             f"{sum(r['ok'] for r in res)}/{len(res)} two-phase, {time.time() - t0:.1f} s")
-    return np.array(X), np.array(Y), bad
+    return np.array(X), np.array(Y), bad, cost
 
 
 def verify(specs, steps: int, n: int = 200, R: float = 40.0):
@@ -200,6 +217,36 @@ def verify(specs, steps: int, n: int = 200, R: float = 40.0):
     cases = [dict(n=n, R=R, A=a, kappa=k, T_over_Tc=t, seed=i) for i, (a, k, t) in enumerate(specs)]
     res = laplace.run_cases(cases, steps, precision="fp32")
     return np.array([r["sigma"] if r["ok"] else np.nan for r in res])
+
+
+def run_accounting(cost: dict, n_targets: int, verify_steps: int, baselines: dict, surrogates: dict,
+                   seconds_training_runs: float) -> dict:
+    """LBM runs needed per target with the training runs counted.  Every training droplet
+    is one run (it costs more lattice updates than a verification run, so updates are also
+    given in units of one verification run: 200^2 cells x verify_steps); amortised over the
+    study's targets, the surrogate's cost per target is its own runs plus training runs /
+    targets, and the network pays off once the targets outnumber training runs / (baseline
+    runs - surrogate runs)."""
+    unit = 200 * 200 * verify_steps
+    train_runs = cost["runs"]
+    train_units = (cost["updates"] + cost["screen_updates"]) / unit
+    out = dict(training_runs=train_runs, training_updates_in_verify_runs=round(train_units, 1),
+               screen_runs=cost["screen_runs"], screen_updates_in_verify_runs=round(cost["screen_updates"] / unit, 2),
+               redraws=cost["redraws"], targets=n_targets,
+               training_runs_per_target=round(train_runs / max(1, n_targets), 2),
+               training_updates_per_target_in_verify_runs=round(train_units / max(1, n_targets), 2),
+               seconds_training_runs=round(seconds_training_runs, 1), baselines=baselines, surrogates={})
+    for name, (runs, runs_cor) in surrogates.items():
+        rows = {}
+        for label, r in (("first_try", runs), ("with_one_correction", runs_cor)):
+            be = {b: (round(train_runs / (v - r), 1) if v > r else None) for b, v in baselines.items()}
+            be_u = {b: (round(train_units / (v - r), 1) if v > r else None) for b, v in baselines.items()}
+            rows[label] = dict(runs_per_target=round(r, 3),
+                               amortised_runs_per_target=round(r + train_runs / max(1, n_targets), 2),
+                               amortised_updates_per_target_in_verify_runs=round(r + train_units / max(1, n_targets), 2),
+                               break_even_targets_by_runs=be, break_even_targets_by_updates=be_u)
+        out["surrogates"][name] = rows
+    return out
 
 
 def _num(x):
@@ -214,13 +261,14 @@ def study(seed: int = 0, n_targets: int = 64, train_batches: int = 4, train_step
     droplet on the verification geometry (200^2, R = 40, `verify_steps` steps)."""
     t_start = time.time()
     if train_geometry == "uneven":
-        X, Y, bad, sized = training_set(train_batches, seed, train_steps, side=side, domains=domains,
-                                        log=log)
+        X, Y, bad, sized, cost = training_set(train_batches, seed, train_steps, side=side,
+                                              domains=domains, log=log)
     elif train_geometry == "verify":
-        X, Y, bad = training_set_fixed(train_batches, seed, verify_steps, domains=domains, log=log)
+        X, Y, bad, cost = training_set_fixed(train_batches, seed, verify_steps, domains=domains, log=log)
         sized, train_steps, side = 0, verify_steps, (200, 200)
     else:
         raise ValueError(f"unknown training geometry {train_geometry!r}")
+    t_trained = time.time()
     surs, hists = {}, {}
     for name, prior in (("plain", False), ("eq28_prior", True)):
         surs[name] = Surrogate(seed=seed, prior_eq28=prior, max_batch=max(1024, len(X)))
@@ -326,7 +374,14 @@ def study(seed: int = 0, n_targets: int = 64, train_batches: int = 4, train_step
                           kappa_sweep=_num(k_sweep[i]), sigma_sweep=_num(sig_sweep[i]))
                      for i in range(n_targets)])
 
+    accounting = run_accounting(cost, int(valid.sum()), verify_steps,
+                                dict(plain_sweep=float(sweep_runs[valid].mean()),
+                                     secant_eq28=float(sec_runs[valid].mean())),
+                                {k: (v["mean_runs"], v["with_one_correction"]["mean_runs"])
+                                 for k, v in sur_rep.items()},
+                                seconds_training_runs=t_trained - t_start)
     rep = dict(
+        accounting=accounting,
         config=dict(seed=seed, n_targets=n_targets, train_batches=train_batches, domains=domains,
                     train_geometry=train_geometry, train_steps=train_steps, verify_steps=verify_steps,
                     side=list(side), verify_lattice=200, verify_radius=40, tolerance=TOLERANCE,

@@ -8,6 +8,7 @@
 * Capillary oscillation (Sec. 4.2) with the Peng-Robinson set-up of Sec. 4:
   the period is within the paper's own error range of Eq. (30).
 """
+import json
 import sys
 
 import numpy as np
@@ -130,3 +131,13 @@ def test_surrogate_needs_fewer_lbm_runs_than_the_methods_without_it(studies):
                key=lambda r: r["mean_runs"])
     assert best["success"] == 1.0
     assert best["mean_runs"] < rep["secant_eq28"]["mean_runs"] <= rep["plain_sweep"]["mean_runs"]
+    # the training runs are counted: every training droplet is one run, amortised per target
+    acc = rep["accounting"]
+    print("[surrogate-accounting] " + json.dumps(acc), flush=True)
+    assert acc["training_runs"] == 256 and acc["targets"] == rep["targets_valid"]
+    for rows in acc["surrogates"].values():
+        for r in rows.values():
+            assert abs(r["amortised_runs_per_target"] - (r["runs_per_target"] + 256 / acc["targets"])) < 0.01
+            if r["runs_per_target"] < acc["baselines"]["plain_sweep"]:
+                want = 256 / (acc["baselines"]["plain_sweep"] - r["runs_per_target"])
+                assert abs(r["break_even_targets_by_runs"]["plain_sweep"] - want) < 0.1
