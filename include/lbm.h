@@ -289,11 +289,17 @@ lbm_status lbm_state_info(const lbm_ctx* ctx, int64_t* step, const void** f_cur,
 typedef struct lbm_batch lbm_batch;
 
 typedef enum {
-  LBM_BATCH_PERSISTENT = 0, /* one launch advances all domains by n steps; each domain's
-                               tiles meet at a per-domain step barrier (bounded wait).
-                               Switched off in this version: lbm_batch_set_launch
-                               returns LBM_EINVAL for it */
-  LBM_BATCH_PER_STEP = 1    /* one launch per step over all tiles, captured in HIP graphs */
+  LBM_BATCH_PERSISTENT = 0, /* one launch advances all domains by the n / 2 pairs of steps
+                               of a call (two-step passes; an odd n ends with one
+                               single-step launch).  The domains are split into one group
+                               per XCD; the workgroups on an XCD take that group's tiles
+                               pair by pair from a queue, and a tile waits for its
+                               domain's previous pair at a per-domain barrier (bounded
+                               wait; a wait past the spin limit aborts the launch, which
+                               lbm_batch_sync reports).  Bitwise the states of the
+                               per-step mode with the same tiles */
+  LBM_BATCH_PER_STEP = 1    /* one launch per step (or per two fused steps) over all
+                               tiles, the launches of a call captured in a HIP graph */
 } lbm_batch_mode;
 
 typedef struct {
@@ -308,10 +314,10 @@ typedef struct {
   int32_t ntiles;           /* tiles over all domains                                 */
   int32_t resident_per_cu;  /* persistent mode: workgroups one CU holds at once       */
   /* input again: */
-  int32_t steps_per_pass;   /* per-step mode: 1, or 2 = two fused steps per launch as in
-                               lbm_launch (tile_x in {128, 256}; an odd count ends with
-                               one single-step launch); 0 = 2 in the per-step mode unless
-                               tile_x is 64, else 1                                     */
+  int32_t steps_per_pass;   /* 1, or 2 = two fused steps per pass as in lbm_launch
+                               (tile_x in {128, 256}; an odd count ends with one
+                               single-step launch); 0 = 2 unless tile_x is 64.  The
+                               persistent mode needs 2                                  */
 } lbm_batch_launch;
 
 /* Creates a batch of n domains with parameters params[0..n).  Allocates one
@@ -327,11 +333,12 @@ lbm_status lbm_batch_create(const lbm_params* params, int32_t n, void* hip_strea
 void lbm_batch_destroy(lbm_batch* b);
 
 /* Chooses the launch mode and tile shape (re-plans the tiles and, in
- * persistent mode, their assignment to a grid no larger than the GPU holds
- * at once).  LBM_EINVAL for an invalid or switched-off choice (the batch then
- * keeps its previous launch); LBM_ENOMEM or LBM_EDEVICE if the new tile lists
- * cannot be placed on the device, after which lbm_batch_step refuses to run
- * until a later call succeeds. */
+ * persistent mode, their grouping by XCD and a grid no larger than the GPU
+ * holds at once).  LBM_EINVAL for an invalid choice, e.g. the persistent mode
+ * with one step per pass or 64-lane tiles (the batch then keeps its previous
+ * launch); LBM_ENOMEM or LBM_EDEVICE if the new tile lists cannot be placed on
+ * the device, after which lbm_batch_step refuses to run until a later call
+ * succeeds. */
 lbm_status lbm_batch_set_launch(lbm_batch* b, const lbm_batch_launch* launch);
 lbm_status lbm_batch_get_launch(const lbm_batch* b, lbm_batch_launch* launch);
 

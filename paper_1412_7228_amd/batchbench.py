@@ -4,8 +4,9 @@
 {64..512}, R = u * side with u ~ U[0.15, 0.35], T/Tc ~ U[0.6, 0.85],
 kappa ~ U[0, 0.8], A ~ U[-0.7, -0.3] (seeded), FP32, CS EOS.  Times the
 per-step launch mode (launches in HIP graphs) with one step per launch and
-with two fused steps per launch, with HIP events on the batch's stream, and
-prints one JSON line: MLUPS over all domains, the launch shapes, and how many
+with two fused steps per launch, and the persistent mode (one launch for all
+pairs of steps of a call), with HIP events on the batch's stream, and prints
+one JSON line: MLUPS over all domains, the launch shapes, and how many
 domains stayed two-phase.
 
 Draws that the method cannot hold (laplace.feasible_batch_draws: a flat slab of
@@ -81,10 +82,11 @@ def main():
         print(f"[batch] autotune {tuned}", flush=True)
     res = {}
     all_modes = {"1": ("per_step", (64, 16), 1), "2x128": ("per_step", (128, 16), 2),
-                 "2x256": ("per_step", (256, 16), 2)}
+                 "2x256": ("per_step", (256, 16), 2), "p256": ("persistent", (256, 16), 2),
+                 "p128": ("persistent", (128, 16), 2)}
     for mode, tile, spp in (all_modes[m] for m in a.modes.split(",")):
         ms = time_mode(b, mode, tile, a.steps, spp)
-        key = f"{mode}{'2' if spp == 2 else ''}_{tile[0]}x{tile[1]}"
+        key = f"{mode}{'2' if spp == 2 and mode == 'per_step' else ''}_{tile[0]}x{tile[1]}"
         res[key] = dict(ms=ms, mlups=cells * a.steps / (ms * 1e-3) / 1e6, tile=list(tile),
                         steps_per_pass=spp, grid=b.launch["grid"], ntiles=b.launch["ntiles"])
         print(f"[batch] {key} {res[key]}", flush=True)

@@ -20,7 +20,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm.so")
-SOURCES = ["lbm_step.hip", "lbm_fields.hip", "lbm_batch.hip", "lbm_mlp.hip", "lbm_api.hip", "lbm_copy.hip"]
+SOURCES = ["lbm_step.hip", "lbm_fields.hip", "lbm_batch.hip", "lbm_persistent.hip", "lbm_mlp.hip",
+           "lbm_api.hip", "lbm_copy.hip"]
 OBJDIR = os.path.join(ROOT, "_build")
 ARCH = os.environ.get("LBM_OFFLOAD_ARCH", "gfx950")
 

@@ -949,7 +949,8 @@ struct lbm_batch {
   std::vector<ModelConsts> m;
   std::vector<Geometry> g;
   std::vector<size_t> off[2];
-  std::vector<unsigned> ntiles;
+  std::vector<unsigned> ntiles;   // single-step tiles of each domain
+  std::vector<unsigned> ntiles2;  // two-step tiles of each domain
   std::vector<bool> inited;
   lbm_precision prec = LBM_FP64;
   int eos = 0;
@@ -968,7 +969,7 @@ struct lbm_batch {
   void* d_tiles = nullptr;
   int* d_group_begin = nullptr;
   int nxcd = 1;               // XCDs of the device: one domain group each (persistent mode)
-  int max_group_tiles = 1;    // tiles of the largest group (bounds the steps of one launch)
+  int max_group_tiles = 1;    // two-step tiles of the largest group (bounds the pairs of one launch)
   unsigned* d_head = nullptr;
   unsigned* d_done = nullptr;
   int* d_err = nullptr;
@@ -988,9 +989,10 @@ struct lbm_batch {
 
 namespace {
 
-// The persistent launch mode stays off until its kernel has passed the GPU
-// tests: an earlier form of it never finished on the GPU.
-constexpr bool kPersistentEnabled = false;
+// The persistent launch mode (lbm_persistent.hip).  An earlier form of its
+// kernel, with a wait loop run by one lane, never finished on the GPU; this
+// switch turns the mode off again should the present form fail its GPU tests.
+constexpr bool kPersistentEnabled = true;
 
 void batch_free_layout(lbm_batch* b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
@@ -1002,19 +1004,25 @@ void batch_free_layout(lbm_batch* b) {
   b->d_group_begin = nullptr;
 }
 
-// Tiles of every domain and the device copies.  Persistent mode: the domains
-// go to one group per XCD (longest processing time first onto the least loaded
-// group) and the tiles are stored group by group, each domain's tiles
-// together, so that a group's queue finishes one domain's step before the next.
+// Tiles of every domain and the device copies.  The single-step tile list
+// (tile_x x tile_y tiles, domain by domain) serves one-step launches; the
+// two-step list (strips of tile_x - 6 stored columns, the same row blocks)
+// serves two-step launches, domain by domain in the per-step mode.  In the
+// persistent mode the two-step list is stored group by group: the domains go
+// to one group per XCD (longest processing time first onto the least loaded
+// group), each domain's tiles together, so that a group's queue finishes one
+// domain's pair of steps before the next.
 lbm_status batch_layout(lbm_batch* b) {
   b->layout_ok = false;  // until every list below is on the device
   HIP_TRY(hipStreamSynchronize(b->stream));
   batch_free_layout(b);
   HIP_TRY(hipMemsetAsync(b->d_err, 0, sizeof(int), b->stream));
-  struct T4 { int d, x0, y0, down; long long cost; };
-  std::vector<T4> tiles;
+  struct T4 { int d, x0, y0, down; };
+  std::vector<T4> tiles, tiles2;
   std::vector<long long> dcost(b->n, 0);
   b->ntiles.assign(b->n, 0);
+  b->ntiles2.assign(b->n, 0);
+  const int w2 = b->tile_x - kStep2Halo;
   for (int d = 0; d < b->n; ++d) {
     Geometry& g = b->g[d];
     g.tile_x = b->tile_x;
@@ -1023,15 +1031,21 @@ lbm_status batch_layout(lbm_batch* b) {
     g.nrowblocks = (g.ny + g.tile_y - 1) / g.tile_y;
     g.nblocks = g.nstrips * g.nrowblocks;
     for (int rb = 0; rb < g.nrowblocks; ++rb)
-      for (int sx = 0; sx < g.nstrips; ++sx) {
-        const int x0 = sx * g.tile_x, y0 = rb * g.tile_y;
-        const long long w = std::min(g.tile_x, g.nx - x0), h = std::min(g.tile_y, g.ny - y0);
-        tiles.push_back({d, x0, y0, rb & 1, w * (h + 2)});
-        dcost[d] += w * (h + 2);
-      }
+      for (int sx = 0; sx < g.nstrips; ++sx) tiles.push_back({d, sx * g.tile_x, rb * g.tile_y, rb & 1});
     b->ntiles[d] = (unsigned)g.nblocks;
+    if (b->fuse == 2) {
+      const int ns = (g.nx + w2 - 1) / w2;
+      for (int rb = 0; rb < g.nrowblocks; ++rb)
+        for (int sx = 0; sx < ns; ++sx) {
+          const long long w = std::min(w2, g.nx - sx * w2), h = std::min(g.tile_y, g.ny - rb * g.tile_y);
+          tiles2.push_back({d, sx * w2, rb * g.tile_y, rb & 1});
+          dcost[d] += (w + kStep2Halo) * (h + 6);  // cells a pass computes, halo included
+        }
+      b->ntiles2[d] = (unsigned)(ns * g.nrowblocks);
+    }
   }
   b->ntile_total = (int)tiles.size();
+  b->ntile2_total = (int)tiles2.size();
   std::vector<int> group_begin;
   if (b->mode == LBM_BATCH_PERSISTENT) {
     HIP_TRY(batch_occupancy(b->prec, b->eos, b->tile_x, &b->per_cu));
@@ -1048,48 +1062,34 @@ lbm_status batch_layout(lbm_batch* b) {
       members[gi].push_back(d);
       load[gi] += dcost[d];
     }
-    std::vector<int> first(b->n + 1, 0);  // tiles were generated domain by domain
-    for (int d = 0; d < b->n; ++d) first[d + 1] = first[d] + (int)b->ntiles[d];
+    std::vector<int> first(b->n + 1, 0);  // two-step tiles were generated domain by domain
+    for (int d = 0; d < b->n; ++d) first[d + 1] = first[d] + (int)b->ntiles2[d];
     std::vector<T4> sorted;
     group_begin.push_back(0);
     for (int gi = 0; gi < ng; ++gi) {
       for (int d : members[gi])
-        for (int t = first[d]; t < first[d + 1]; ++t) sorted.push_back(tiles[t]);
+        for (int t = first[d]; t < first[d + 1]; ++t) sorted.push_back(tiles2[t]);
       group_begin.push_back((int)sorted.size());
     }
     b->max_group_tiles = 1;
     for (int gi = 0; gi < ng; ++gi)
       b->max_group_tiles = std::max(b->max_group_tiles, group_begin[gi + 1] - group_begin[gi]);
-    tiles.swap(sorted);
+    tiles2.swap(sorted);
   } else {
     b->grid = b->ntile_total;
     group_begin.assign(2, 0);
   }
-  // two-step tiles (per-step mode with two steps per launch): strips of
-  // tile_x - 6 stored columns, the same row blocks
-  std::vector<unsigned char> ht2;
-  b->ntile2_total = 0;
-  if (b->mode == LBM_BATCH_PER_STEP && b->fuse == 2) {
-    const size_t tb2 = batch_tile_bytes();
-    const int w = b->tile_x - kStep2Halo;
-    for (int d = 0; d < b->n; ++d) {
-      const Geometry& g = b->g[d];
-      const int ns = (g.nx + w - 1) / w;
-      for (int rb = 0; rb < g.nrowblocks; ++rb)
-        for (int sx = 0; sx < ns; ++sx) {
-          ht2.resize(ht2.size() + tb2);
-          batch_fill_tile(d, sx * w, rb * g.tile_y, rb & 1, ht2.data() + ht2.size() - tb2);
-          ++b->ntile2_total;
-        }
-    }
-  }
   const size_t db = batch_domain_bytes(b->prec), tb = batch_tile_bytes();
-  std::vector<unsigned char> hd(db * b->n), ht(tb * tiles.size());
+  std::vector<unsigned char> hd(db * b->n), ht(tb * tiles.size()), ht2(tb * tiles2.size());
+  // the persistent barrier counts a domain's two-step tiles
   for (int d = 0; d < b->n; ++d)
     batch_fill_domain(b->prec, b->g[d], b->m[d], static_cast<char*>(b->arena) + b->off[0][d],
-                      static_cast<char*>(b->arena) + b->off[1][d], b->ntiles[d], hd.data() + d * db);
+                      static_cast<char*>(b->arena) + b->off[1][d], b->fuse == 2 ? b->ntiles2[d] : b->ntiles[d],
+                      hd.data() + d * db);
   for (size_t t = 0; t < tiles.size(); ++t)
     batch_fill_tile(tiles[t].d, tiles[t].x0, tiles[t].y0, tiles[t].down, ht.data() + t * tb);
+  for (size_t t = 0; t < tiles2.size(); ++t)
+    batch_fill_tile(tiles2[t].d, tiles2[t].x0, tiles2[t].y0, tiles2[t].down, ht2.data() + t * tb);
   HIP_TRY(hipMalloc(&b->d_dom, hd.size()));
   HIP_TRY(hipMalloc(&b->d_tiles, ht.size()));
   HIP_TRY(hipMalloc(&b->d_group_begin, group_begin.size() * sizeof(int)));
@@ -1122,26 +1122,31 @@ BatchRun batch_run(const lbm_batch* b, int nsteps, int parity) {
   return r;
 }
 
-// Launches that n steps take: one per step, or n / 2 two-step launches and a
-// single step for an odd n.
+// Buffer swaps that n steps take: one per step, or one per pair of steps and
+// one for an odd last step.
 int batch_launches(const lbm_batch* b, int n) {
-  return (b->mode == LBM_BATCH_PER_STEP && b->fuse == 2) ? n / 2 + n % 2 : n;
+  return b->fuse == 2 ? n / 2 + n % 2 : n;
 }
 
-// Enqueues n steps: persistent = queue/counter reset, one launch and the
-// completion check; per-step = one launch per step (or per two steps) with
-// alternating buffers.
+// Enqueues n steps: persistent = queue/counter reset, one launch of n / 2
+// pairs and the completion check; per-step = one launch per step (or per two
+// steps) with alternating buffers; either way an odd last step is one
+// single-step launch.
 hipError_t batch_enqueue(lbm_batch* b, int n) {
   hipError_t e = hipSuccess;
-  if (b->mode == LBM_BATCH_PERSISTENT) {
-    const BatchRun r = batch_run(b, n, b->parity);
-    e = launch_batch_reset(r, b->n, b->stream);
-    if (e == hipSuccess) e = launch_batch(b->prec, b->eos, b->tile_x, true, r, b->stream);
-    if (e == hipSuccess) e = launch_batch_check(b->prec, r, b->n, b->stream);
-    return e;
-  }
   int launch = 0, left = n;
-  if (b->fuse == 2) {
+  if (b->mode == LBM_BATCH_PERSISTENT) {
+    const int pairs = n / 2;
+    if (pairs > 0) {
+      BatchRun r = batch_run(b, pairs, b->parity);
+      r.tiles = b->d_tiles2;
+      e = launch_batch_reset(r, b->n, b->stream);
+      if (e == hipSuccess) e = launch_batch_persistent(b->prec, b->eos, b->tile_x, r, b->stream);
+      if (e == hipSuccess) e = launch_batch_check(b->prec, r, b->n, b->stream);
+    }
+    launch = pairs;
+    left = n - 2 * pairs;
+  } else if (b->fuse == 2) {
     for (; left >= 2 && e == hipSuccess; left -= 2, ++launch) {
       BatchRun r = batch_run(b, 2, (b->parity + launch) & 1);
       r.tiles = b->d_tiles2;
@@ -1149,9 +1154,11 @@ hipError_t batch_enqueue(lbm_batch* b, int n) {
       e = launch_batch_step2(b->prec, b->eos, b->tile_x, r, b->stream);
     }
   }
-  for (; left > 0 && e == hipSuccess; --left, ++launch)
-    e = launch_batch(b->prec, b->eos, b->tile_x, false, batch_run(b, 1, (b->parity + launch) & 1),
-                     b->stream);
+  for (; left > 0 && e == hipSuccess; --left, ++launch) {
+    BatchRun r = batch_run(b, 1, (b->parity + launch) & 1);
+    r.grid = b->ntile_total;
+    e = launch_batch(b->prec, b->eos, b->tile_x, r, b->stream);
+  }
   return e;
 }
 
@@ -1300,12 +1307,11 @@ lbm_status lbm_batch_set_launch(lbm_batch* b, const lbm_batch_launch* l) {
   if (l->mode == LBM_BATCH_PERSISTENT && !kPersistentEnabled)
     return fail(LBM_EINVAL, "persistent batch mode is switched off in this version of the library (its kernel has not "
                             "passed on a GPU); use LBM_BATCH_PER_STEP");
-  // steps_per_pass 0: two, unless the mode or a 64-wide tile asks for one
-  const int fuse = l->steps_per_pass ? l->steps_per_pass
-                                     : ((l->mode == LBM_BATCH_PER_STEP && l->tile_x != 64) ? 2 : 1);
+  // steps_per_pass 0: two, unless a 64-wide tile asks for one
+  const int fuse = l->steps_per_pass ? l->steps_per_pass : (l->tile_x != 64 ? 2 : 1);
   if (fuse != 1 && fuse != 2) return fail(LBM_EINVAL, "steps_per_pass %d not in {1, 2}", fuse);
-  if (fuse == 2 && l->mode != LBM_BATCH_PER_STEP)
-    return fail(LBM_EINVAL, "two steps per launch needs the per-step mode");
+  if (fuse != 2 && l->mode == LBM_BATCH_PERSISTENT)
+    return fail(LBM_EINVAL, "the persistent mode runs two steps per pass");
   const int tx = l->tile_x ? l->tile_x : (fuse == 2 ? 256 : 64), ty = l->tile_y ? l->tile_y : (fuse == 2 ? 16 : 32);
   if (tx != 64 && tx != 128 && tx != 256) return fail(LBM_EINVAL, "tile_x %d not in {64,128,256}", tx);
   if (fuse == 2 && tx == 64) return fail(LBM_EINVAL, "tile_x 64 too narrow for two steps per launch");
@@ -1332,7 +1338,7 @@ lbm_status lbm_batch_get_launch(const lbm_batch* b, lbm_batch_launch* l) {
   l->resident_per_cu = b->per_cu;
   l->steps_per_pass = b->fuse;
   if (b->fuse == 2) {
-    l->grid = b->ntile2_total;
+    l->grid = b->mode == LBM_BATCH_PERSISTENT ? b->grid : b->ntile2_total;
     l->ntiles = b->ntile2_total;
   }
   return LBM_OK;
@@ -1365,13 +1371,14 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t n) {
     if (!b->inited[d]) return fail(LBM_ESTATE, "batch domain %d not initialised", d);
   if (!b->layout_ok)
     return fail(LBM_ESTATE, "batch has no launch layout (the last lbm_batch_set_launch failed); set it again");
-  // persistent mode: the whole call is one launch, chunked only where a group's
-  // queue (tiles x steps) would pass 2^31; per-step mode: one graph per call of
-  // up to 32,768 steps (the 20,000 steps of a droplet study are one graph launch
-  // of 10,000 kernel nodes; capturing and instantiating it takes about 20 ms and
-  // its replay runs as fast as shorter graphs)
+  // persistent mode: the whole call is one launch (plus a single step for an
+  // odd count), chunked only where a group's queue (tiles x pairs) would pass
+  // 2^31; per-step mode: one graph per call of up to 32,768 steps (the 20,000
+  // steps of a droplet study are one graph launch of 10,000 kernel nodes;
+  // capturing and instantiating it takes about 20 ms and its replay runs as
+  // fast as shorter graphs)
   const int64_t chunk = b->mode == LBM_BATCH_PERSISTENT
-                            ? std::max<int64_t>(1, ((1ll << 31) - 1) / b->max_group_tiles)
+                            ? 2 * std::max<int64_t>(1, ((1ll << 31) - 1) / b->max_group_tiles)
                             : 32768;
   int64_t left = n;
   while (left > 0) {

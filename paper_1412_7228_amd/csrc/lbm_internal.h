@@ -89,10 +89,11 @@ size_t batch_tile_bytes();
 void batch_fill_domain(lbm_precision prec, const Geometry& g, const ModelConsts& m, void* fa,
                        void* fb, unsigned ntiles, void* out);
 void batch_fill_tile(int domain, int x0, int y0, int down, void* out);
-hipError_t batch_occupancy(lbm_precision prec, int eos, int tile_x, int* per_cu);
-// One batch launch.  Persistent mode: the tiles of XCD group g are
+// Persistent mode (lbm_persistent.hip): one launch of npairs two-step passes
+// over the two-step tiles, grouped by XCD.  The tiles of XCD group g are
 // tiles[group_begin[g] .. group_begin[g+1]), head[g] is that group's queue
-// position, done[d] counts the finished tiles of domain d, err collects aborts.
+// position, done[d] counts the finished tiles of domain d, err collects
+// aborts (1: a wait passed the spin limit; 2: a domain missed tiles).
 struct BatchRun {
   const void* dom;
   const void* tiles;
@@ -101,16 +102,20 @@ struct BatchRun {
   unsigned* head;
   unsigned* done;
   int* err;
-  int grid, nsteps, parity;
+  int grid, nsteps, parity;  // nsteps: steps (per-step kernels) or pairs of steps (persistent)
   long long spin_limit;
 };
-hipError_t launch_batch(lbm_precision prec, int eos, int tile_x, bool persistent, const BatchRun& r,
-                        hipStream_t s);
+// Workgroups of the persistent kernel (tile_x in {128, 256}) that one CU holds at once.
+hipError_t batch_occupancy(lbm_precision prec, int eos, int tile_x, int* per_cu);
+hipError_t launch_batch_persistent(lbm_precision prec, int eos, int tile_x, const BatchRun& r,
+                                   hipStream_t s);
+hipError_t launch_batch_reset(const BatchRun& r, int ndomains, hipStream_t s);
+hipError_t launch_batch_check(lbm_precision prec, const BatchRun& r, int ndomains, hipStream_t s);
+// Per-step mode (lbm_batch.hip): one single-step launch over the tile list.
+hipError_t launch_batch(lbm_precision prec, int eos, int tile_x, const BatchRun& r, hipStream_t s);
 // Per-step mode, two fused steps per launch over the two-step tile list.
 hipError_t launch_batch_step2(lbm_precision prec, int eos, int tile_x, const BatchRun& r,
                               hipStream_t s);
-hipError_t launch_batch_reset(const BatchRun& r, int ndomains, hipStream_t s);
-hipError_t launch_batch_check(lbm_precision prec, const BatchRun& r, int ndomains, hipStream_t s);
 
 // Surrogate network (lbm_mlp.hip).
 int mlp_param_count();

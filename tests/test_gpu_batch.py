@@ -1,11 +1,12 @@
 """The batched engine (lbm_batch_*): every domain of an uneven batch must equal the
-same lattice run alone (bitwise: same per-tile arithmetic) and the oracle.
+same lattice run alone (bitwise: same per-tile arithmetic) and the oracle, in the
+per-step mode (one launch per step or per two steps) and in the persistent mode (one
+launch for all pairs of steps of a call, per-domain barriers inside it).
 
-The persistent launch mode is switched off in the library (set_launch rejects it):
-an earlier form of its kernel never finished on the GPU, because a loop whose end
-depended on thread 0 was compiled into an inner loop that the other lanes of the
-wave never left.  Its tests stay here, skipped, until the restructured kernel has
-run on a GPU."""
+The persistent kernel's scheduling protocol and the shape of its compiled loops are
+checked on the CPU first (tests/test_persistent_protocol.py): an earlier form of its
+barrier wait, a loop run by thread 0 alone, never finished on the GPU.  Every case
+here prints its name before it runs."""
 import sys
 
 import numpy as np
@@ -15,10 +16,6 @@ from oracle import thermo as th
 from paper_1412_7228_amd import inputs
 
 pytestmark = pytest.mark.gpu
-
-PERSISTENT_OFF = ("persistent batch mode is switched off: an earlier form of its kernel hung "
-                  "on the GPU (lane-divergent inner loop); the restructured kernel has not run "
-                  "on a GPU yet")
 
 
 def say(msg):
@@ -62,8 +59,7 @@ def _rho0(i, d):
     return inputs.droplet(d["nx"], d["ny"], d["R"], rl, rv, W=4.0, noise=1e-2, seed=i)
 
 
-@pytest.mark.parametrize("mode", ["per_step", "per_step2",
-                                  pytest.param("persistent", marks=pytest.mark.skip(reason=PERSISTENT_OFF))])
+@pytest.mark.parametrize("mode", ["per_step", "per_step2", "persistent"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_batch_equals_single_lattices(lbm, mode, precision):
     say(f"batch {mode} {precision}")
@@ -72,6 +68,9 @@ def test_batch_equals_single_lattices(lbm, mode, precision):
     if mode == "per_step2":  # two fused steps per launch; 7 and 30 steps end on single steps
         b.set_launch("per_step", 128, 16, steps_per_pass=2)
         assert b.launch["steps_per_pass"] == 2
+    elif mode == "persistent":  # one launch of 3 (then 15) pairs, then one single step
+        b.set_launch("persistent", 128, 16)
+        assert b.launch["mode"] == "persistent" and b.launch["steps_per_pass"] == 2
     else:
         b.set_launch(mode, 64, 16)
     for i, d in enumerate(DOMAINS):
@@ -106,21 +105,20 @@ def test_batch_matches_oracle_fp64(lbm, oracle_mod):
         assert obs[i]["step"] == 40
 
 
-@pytest.mark.skip(reason=PERSISTENT_OFF)
 def test_persistent_barrier_timeout_aborts_cleanly(lbm):
-    """Spin limit 0: any tile that must wait gives up, sets the error flag and every
-    workgroup leaves; the launch ends and the host sees LBM_EDEVICE."""
-    say("batch forced barrier timeout")
+    """Spin limit 0 (forced from the host): a tile that finds its domain's previous pair
+    unfinished gives up at once, sets the error flag and every workgroup leaves; the
+    launch ends and the host sees LBM_EDEVICE.  The batch runs again after a re-plan."""
+    say("batch persistent: forced barrier timeout (spin limit 0)")
     cfgs = _cfgs("fp32")
     b = lbm.Batch(cfgs)
-    b.set_launch("persistent", 64, 4, spin_limit=0, force_spin_limit=True)
+    b.set_launch("persistent", 128, 4, spin_limit=0, force_spin_limit=True)
     for i, d in enumerate(DOMAINS):
         b.init_field(i, _rho0(i, d))
     b.step(50)
     with pytest.raises(lbm.LBMError) as ei:
         b.sync()
     assert ei.value.status == -3
-    # the batch is usable again after a normal re-plan
     b.set_launch("per_step", 64, 16)
     b.step(2)
     b.sync()
@@ -132,12 +130,12 @@ def test_batch_rejects_mixed_eos(lbm):
         lbm.Batch([dict(nx=16, ny=16, eos="cs"), dict(nx=16, ny=16, eos="vdw", K=0.3, T_over_Tc=0.9)])
 
 
-@pytest.mark.skip(reason=PERSISTENT_OFF)
-@pytest.mark.parametrize("tile", [(64, 8), (128, 16), (256, 8)])
+@pytest.mark.parametrize("tile", [(128, 16), (256, 8), (256, 16)])
 def test_persistent_many_domains_equals_per_step(lbm, tile):
-    """48 uneven domains (more than one per XCD group), several launches of the
-    persistent engine, multi-wave workgroups: bitwise equal to per-step launches."""
-    say(f"batch persistent many domains tile {tile}")
+    """48 uneven domains (several per XCD group), three calls (1, 99 and 200 steps: a
+    single step alone, 49 pairs and a single step, 100 pairs): the persistent engine is
+    bitwise equal to per-step launches of the same tiles."""
+    say(f"batch persistent, 48 domains, tile {tile}")
     rng = np.random.default_rng(5)
     e = th.carnahan_starling()
     _, Tc = th.critical_point(e)
@@ -153,89 +151,33 @@ def test_persistent_many_domains_equals_per_step(lbm, tile):
     runs = {}
     for mode in ("persistent", "per_step"):
         b = lbm.Batch(cfgs)
-        b.set_launch(mode, *tile)
+        b.set_launch(mode, *tile, steps_per_pass=2)
         for i, r in enumerate(rhos):
             b.init_field(i, r)
         for k in (1, 99, 200):
             b.step(k)
         b.sync()
+        assert all(o["step"] == 300 for o in b.observables())
         runs[mode] = [b.f_soa(i) for i in range(len(cfgs))]
+        b.close()
     for i in range(len(cfgs)):
         assert np.array_equal(runs["persistent"][i], runs["per_step"][i], equal_nan=True), i
 
 
-def test_persistent_mode_is_rejected_while_switched_off(lbm):
-    say("batch persistent mode rejected")
+def test_persistent_mode_needs_two_steps_per_pass(lbm):
+    """The persistent engine runs two-step tiles: one step per pass or 64-lane tiles are
+    refused (LBM_EINVAL) and the batch keeps its plan and still runs."""
+    say("batch persistent: refused launch shapes")
     b = lbm.Batch(_cfgs("fp32")[:2])
-    with pytest.raises(lbm.LBMError) as ei:
-        b.set_launch("persistent", 64, 16)
-    assert ei.value.status == -1
-    # the batch keeps its per-step plan and still runs
+    for kw in (dict(tile_x=64, tile_y=16), dict(tile_x=128, tile_y=16, steps_per_pass=1)):
+        with pytest.raises(lbm.LBMError) as ei:
+            b.set_launch("persistent", **kw)
+        assert ei.value.status == -1
+    assert b.launch["mode"] == "per_step"
     for i, d in enumerate(DOMAINS[:2]):
         b.init_field(i, _rho0(i, d))
     b.step(3)
     b.sync()
-
-
-@pytest.mark.parametrize("tile,precision", [((128, 8), "fp32"), ((256, 16), "fp32"), ((256, 13), "fp32"),
-                                            ((128, 16), "fp64")])
-def test_two_step_batch_many_domains_equals_single_steps(lbm, tile, precision):
-    """48 uneven domains, two fused steps per launch against one step per launch
-    (bitwise), over several calls with odd and even step counts."""
-    say(f"batch two-step many domains tile {tile} {precision}")
-    rng = np.random.default_rng(7)
-    e = th.carnahan_starling()
-    _, Tc = th.critical_point(e)
-    cfgs, rhos = [], []
-    for i in range(48):
-        nx, ny = int(rng.integers(12, 300)), int(rng.integers(12, 300))
-        T = float(rng.uniform(0.7, 0.85))
-        rv, rl = th.maxwell(e, T * Tc)
-        cfgs.append(dict(nx=nx, ny=ny, eos="cs", precision=precision, T_over_Tc=T,
-                         A=float(rng.uniform(-0.7, -0.3)), kappa=float(rng.uniform(0.0, 0.8))))
-        rhos.append(inputs.droplet(nx, ny, max(1.0, 0.3 * min(nx, ny)), rl, rv, W=4.0, noise=1e-2,
-                                   seed=200 + i))
-    runs = {}
-    for spp in (1, 2):
-        b = lbm.Batch(cfgs)
-        b.set_launch("per_step", tile[0], tile[1], steps_per_pass=spp)
-        for i, r in enumerate(rhos):
-            b.init_field(i, r)
-        for k in (1, 64, 99, 100):
-            b.step(k)
-        b.sync()
-        runs[spp] = [b.f_soa(i) for i in range(len(cfgs))]
-    for i in range(len(cfgs)):
-        assert np.array_equal(runs[2][i], runs[1][i], equal_nan=True), i
-
-
-@pytest.mark.parametrize("steps_per_pass", [1, 2])
-def test_failing_domain_leaves_the_others_untouched(lbm, steps_per_pass):
-    """A domain that blows up (a drop at 0.95 of the Carnahan-Starling packing limit:
-    the oracle turns every cell non-finite within 10 steps) is reported through its
-    own observables; the other domains of the same launches are bitwise the lattices
-    run alone and report no fault."""
-    say(f"batch with one failing domain, {steps_per_pass} step(s) per launch")
-    cfgs = _cfgs("fp32")
-    bad = 2
-    rho = [_rho0(i, d) for i, d in enumerate(DOMAINS)]
-    nx, ny = DOMAINS[bad]["nx"], DOMAINS[bad]["ny"]
-    rho[bad] = inputs.droplet(nx, ny, 8.0, 0.95, 0.01, W=2.0, noise=1e-3, seed=1)
-    b = lbm.Batch(cfgs)
-    b.set_launch("per_step", 128 if steps_per_pass == 2 else 64, 16, steps_per_pass=steps_per_pass)
-    for i in range(len(DOMAINS)):
-        b.init_field(i, rho[i])
-    b.step(40)
-    obs = b.observables()
-    assert obs[bad]["n_nonfinite"] > 0
-    for i, c in enumerate(cfgs):
-        if i == bad:
-            continue
-        assert obs[i]["n_nonfinite"] == 0 and obs[i]["n_domain"] == 0, i
-        lat = lbm.Lattice(c)
-        lat.init_field(rho[i])
-        lat.step(40)
-        assert np.array_equal(b.f_soa(i), lat.f_soa()), i
 
 
 def test_one_graph_per_call_replayed(lbm):
