@@ -192,7 +192,9 @@ lbm_status lbm_init_field(lbm_ctx* ctx, const double* rho, const double* ux, con
  * precision.  Resets the step counter.  LBM_EINVAL on NULL. */
 lbm_status lbm_set_distributions(lbm_ctx* ctx, const double* f);
 
-/* Enqueues n >= 0 time steps on the context stream and returns.  With two
+/* Enqueues n >= 0 time steps of the update above (Eq. 1 with the force of
+ * Eq. 9, the term of Eq. 23 and the collision of Eq. 25, Sec. 2 and
+ * Sec. 3.2.1) on the context stream and returns.  With two
  * steps per pass, each run of 64 two-step launches is a replay of a HIP graph
  * captured on a stream of the context's own (kernels only; cached per starting
  * buffer and launch shape) and the remaining launches go one by one; the

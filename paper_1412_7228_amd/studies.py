@@ -13,6 +13,9 @@ construction, everything after that from the GPU.
 * ``asweep``      -- method 1 (Sec. 3.1): sigma of a R = 20 droplet on 100 x 100
   and the flat-interface densities for A from -0.9 to 0.99 (vdW, K = 0.3,
   0.9 Tc).
+* ``kappa_sweep`` -- method 2 (Sec. 3.2.2): sigma of the same droplet and the
+  flat-interface densities for kappa from 0 to 0.99 (vdW, K = 0.3, 0.9 Tc,
+  A = -0.5), against the (1 - kappa) law of Eq. (28) and Table 1.
 * ``stability``   -- the lowest temperature at which the model stays stable
   (Sec. 3.1.2 and Table 2) for A = -0.5 and 0.5 and every kappa of Table 2.
 * ``pr_laplace``  -- the Peng-Robinson Laplace test of Sec. 4.1 (120 x 120,
@@ -120,6 +123,34 @@ def a_sweep(As=None, steps: int = 20000, precision: str = "fp64") -> dict:
                 rows=rows, gas_density_shift_A099_to_Am09=shift)
 
 
+def kappa_sweep(kappas=(0.0, 0.2, 0.5, 0.7, 0.9, 0.99), steps: int = 20000,
+                precision: str = "fp64") -> dict:
+    """Method 2 (Sec. 3.2.2, Table 1, Fig. 3): for each kappa the R = 20 vdW droplet on
+    100 x 100 (A = -0.5, 0.9 Tc, K = 0.3) and the flat interface, one batch: sigma by the
+    Laplace law, sigma / sigma(kappa = 0) against 1 - kappa (Eq. 28), and the flat
+    coexistence densities, which must not move with kappa (Table 1)."""
+    cfgs, rhos = [], []
+    for k in kappas:
+        cfg = dict(VDW_SEC3, nx=100, ny=100, T_over_Tc=0.9, A=-0.5, kappa=float(k), precision=precision)
+        rv, rl = lbm.coexistence(cfg)
+        cfgs.append(cfg)
+        rhos.append(inputs.droplet(100, 100, 20.0, rl, rv, W=5.0, noise=0.0))
+        cfgs.append(dict(cfg, ny=4))
+        rhos.append(inputs.slab(100, 4, rl, rv, W=5.0))
+    obs = _run_batch(cfgs, rhos, steps, tile=(128, 16))
+    rows = []
+    s0 = obs[0]["sigma"] if stable(obs[0]) else None
+    for i, k in enumerate(kappas):
+        d, f = obs[2 * i], obs[2 * i + 1]
+        sig = _finite(d["sigma"]) if stable(d) else None
+        rows.append(dict(kappa=float(k), sigma=sig,
+                         sigma_ratio=(sig / s0) if (sig and s0) else None,
+                         linear_law=1.0 - float(k), flat_rho_l=_finite(f["rho_max"]),
+                         flat_rho_v=_finite(f["rho_min"]), droplet_stable=stable(d), flat_stable=stable(f)))
+    return dict(study="kappa_sweep", eos="vdw", K=0.3, T_over_Tc=0.9, A=-0.5, steps=steps,
+                precision=precision, rows=rows)
+
+
 def stability_scan(As=(-0.5, 0.5), kappas=(0.0, 0.2, 0.5, 0.7, 0.9, 0.99), temps=None,
                    geometry: str = "droplet", steps: int = 20000, precision: str = "fp64") -> dict:
     temps = list(np.round(np.arange(0.60, 0.905, 0.01), 3)) if temps is None else list(temps)
@@ -202,7 +233,7 @@ def oscillation_study(kappas=(-1.0, 0.0, 0.5), nu_liquid=(0.1, 0.05), nu_gas: fl
                 precision=precision, **PR_SEC4, rows=rows)
 
 
-STUDIES = dict(laplace=laplace_sweep, asweep=a_sweep, stability=stability_scan,
+STUDIES = dict(laplace=laplace_sweep, asweep=a_sweep, kappa_sweep=kappa_sweep, stability=stability_scan,
                pr_laplace=pr_laplace, oscillation=oscillation_study)
 
 

@@ -102,6 +102,25 @@ def test_method1_table1_and_sigma_on_gpu(studies):
     assert 0.22 < rep["gas_density_shift_A099_to_Am09"] < 0.28
 
 
+def test_method2_kappa_sweep_on_gpu(studies):
+    """Sec. 3.2.2 on the GPU (FP64, batched engine), the vdW droplet and flat interface at
+    kappa = 0, 0.2, 0.5, 0.7, 0.9, 0.99: sigma falls linearly in (1 - kappa) (Eq. 28; Fig. 3)
+    within 3% up to kappa = 0.9; sigma = 0.0459, 0.00448 and 0.000452 (paper, kappa = 0, 0.9,
+    0.99) within 5%; and the flat densities stay at Table 1's 5.79198 / 1.46621 for every
+    kappa, to every printed digit."""
+    say("method 2 kappa sweep (vdW, droplet + flat, FP64)")
+    rep = studies.kappa_sweep(steps=20000)
+    rows = {r["kappa"]: r for r in rep["rows"]}
+    print(json.dumps(rep["rows"]), flush=True)
+    for k, r in rows.items():
+        assert r["droplet_stable"] and r["flat_stable"], k
+        assert round(r["flat_rho_l"], 5) == 5.79198 and round(r["flat_rho_v"], 5) == 1.46621, k
+        if 0.0 < k <= 0.9:
+            assert abs(r["sigma_ratio"] / (1 - k) - 1) < 0.03, (k, r["sigma_ratio"])
+    for k, want in ((0.0, 0.0459), (0.9, 0.00448), (0.99, 0.000452)):
+        assert abs(rows[k]["sigma"] / want - 1) < 0.05, (k, rows[k]["sigma"])
+
+
 def test_pr_laplace_law_and_kappa_scaling(studies):
     """Sec. 4.1 with Peng-Robinson (0.8 Tc, A = -0.3, K = 0.5, 120^2): dp * R_e constant over
     R = 20..40 within 5% at kappa = 0, and sigma(kappa)/sigma(0) within 6% of 1 - kappa
