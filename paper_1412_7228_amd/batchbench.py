@@ -14,6 +14,7 @@ the draw's parameters faults, collapses or loses its second phase) are redrawn
 from the same seeded stream, and the redraws are reported.
 
     python -m paper_1412_7228_amd.batchbench [--steps 20000] [--domains 256] [--no-screen]
+        [--modes 1,2x128,2x256,p256] [--save-draws F | --load-draws F]
 """
 from __future__ import annotations
 
@@ -27,11 +28,16 @@ from . import autotune, inputs, laplace, lbm
 
 
 def build(domains: int, seed: int, precision: str = "fp32", screen: bool = True,
-          max_ratio: float | None = None):
+          max_ratio: float | None = None, draws_file: str | None = None):
     """The batch of `domains` droplets from the seeded draw stream: the first feasible
-    draws (laplace.feasible_batch_draws) unless screen is False.  Returns (batch, cases,
-    cells, screen report)."""
-    if screen:
+    draws (laplace.feasible_batch_draws) unless screen is False, or the draws (and screen
+    report) stored in `draws_file` by an earlier run.  Returns (batch, cases, cells,
+    screen report)."""
+    if draws_file:
+        with open(draws_file) as fh:
+            saved = json.load(fh)
+        draws, report = saved["draws"], saved["report"]
+    elif screen:
         draws, report = laplace.feasible_batch_draws(domains, seed, max_ratio=max_ratio)
     else:
         draws, report = inputs.batch_draws(domains, seed), None
@@ -69,10 +75,19 @@ def main():
     ap.add_argument("--no-screen", action="store_true", help="keep infeasible draws (no redraw)")
     ap.add_argument("--max-ratio", type=float, default=laplace.SCREEN_MAX_RATIO,
                     help="screen: largest flat density ratio kept (0: no cap)")
-    ap.add_argument("--modes", default="1,2x128,2x256", help="launch modes to time")
+    ap.add_argument("--modes", default="1,2x128,2x256,p256", help="launch modes to time")
+    ap.add_argument("--save-draws", default=None, help="write the (screened) draws to this JSON file")
+    ap.add_argument("--load-draws", default=None,
+                    help="take the draws from a file written by --save-draws (no screen run; for profiling)")
     a = ap.parse_args()
     t0 = time.time()
-    b, cases, cells, report = build(a.domains, a.seed, screen=not a.no_screen, max_ratio=a.max_ratio or None)
+    b, cases, cells, report = build(a.domains, a.seed, screen=not a.no_screen, max_ratio=a.max_ratio or None,
+                                    draws_file=a.load_draws)
+    if a.save_draws:
+        with open(a.save_draws, "w") as fh:
+            json.dump(dict(draws=[dict(nx=c["n"], ny=c["n"], R=c["R"], T_over_Tc=c["T_over_Tc"], A=c["A"],
+                                       kappa=c["kappa"], seed=c["seed"], screen_ratio=c["screen_ratio"])
+                                  for c in cases], report=report), fh)
     redraws = None if report is None else report["redraws"]
     print(f"[batch] {a.domains} domains, {cells} cells, {redraws} redraws, setup {time.time() - t0:.1f} s",
           flush=True)
