@@ -91,13 +91,13 @@ def parse():
     ap.add_argument("--no-e2e", action="store_true", help="skip the end-to-end small workloads")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--tile", type=str, default="", help="tile_x,tile_y of the step kernel")
-    ap.add_argument("--copy-mib", type=int, default=1024,
+    ap.add_argument("--copy-mib", type=int, default=2048,
                     help="size of the device-to-device copy timed as the practical bandwidth ceiling "
                          "(0 = skip); under a counter profiler it calibrates FETCH_SIZE/WRITE_SIZE")
     return ap.parse_args()
 
 
-def copy_bandwidth(mib, reps=10):
+def copy_bandwidth(mib, reps=40):
     """The practical HBM ceiling: a device copy of `mib` MiB (read + write bytes / time),
     by the library's hand-written copy kernel (lbm_copy_bytes: one 16-byte load and store
     per lane) and by torch's copy, each timed with HIP events on torch's stream."""
