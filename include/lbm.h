@@ -307,7 +307,8 @@ typedef enum {
 typedef struct {
   int32_t mode;             /* lbm_batch_mode                                         */
   int32_t tile_x, tile_y;   /* tile of every domain; 0 = default (256 x 16 with two
-                               steps per launch, 64 x 32 with one)                   */
+                               steps per launch, 256 x 24 in the persistent mode,
+                               64 x 32 with one step per launch)                      */
   int64_t spin_limit;       /* persistent mode: polls before a barrier wait gives up;
                                0 = default (2^20, about a second)                      */
   int32_t force_spin_limit; /* non-zero with spin_limit 0: use 0 (test of the abort path) */

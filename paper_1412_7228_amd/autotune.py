@@ -20,7 +20,8 @@ LATTICE_CANDIDATES = [(256, 16, 1), (256, 64, 1), (128, 32, 1), (64, 32, 1),
 # the library for now
 BATCH_CANDIDATES = [("per_step", 64, 16, 1), ("per_step", 64, 32, 1), ("per_step", 128, 16, 1),
                     ("per_step", 128, 8, 2), ("per_step", 128, 16, 2), ("per_step", 128, 32, 2),
-                    ("per_step", 256, 8, 2), ("per_step", 256, 16, 2), ("per_step", 256, 32, 2)]
+                    ("per_step", 256, 8, 2), ("per_step", 256, 16, 2), ("per_step", 256, 32, 2),
+                    ("persistent", 256, 16, 2), ("persistent", 256, 24, 2), ("persistent", 256, 32, 2)]
 
 
 def cache_path() -> str:

@@ -97,8 +97,8 @@ def main():
         print(f"[batch] autotune {tuned}", flush=True)
     res = {}
     all_modes = {"1": ("per_step", (64, 16), 1), "2x128": ("per_step", (128, 16), 2),
-                 "2x256": ("per_step", (256, 16), 2), "p256": ("persistent", (256, 16), 2),
-                 "p128": ("persistent", (128, 16), 2)}
+                 "2x256": ("per_step", (256, 16), 2), "p256": ("persistent", (256, 24), 2),
+                 "p256x16": ("persistent", (256, 16), 2), "p128": ("persistent", (128, 16), 2)}
     for mode, tile, spp in (all_modes[m] for m in a.modes.split(",")):
         ms = time_mode(b, mode, tile, a.steps, spp)
         key = f"{mode}{'2' if spp == 2 and mode == 'per_step' else ''}_{tile[0]}x{tile[1]}"

@@ -1312,7 +1312,10 @@ lbm_status lbm_batch_set_launch(lbm_batch* b, const lbm_batch_launch* l) {
   if (fuse != 1 && fuse != 2) return fail(LBM_EINVAL, "steps_per_pass %d not in {1, 2}", fuse);
   if (fuse != 2 && l->mode == LBM_BATCH_PERSISTENT)
     return fail(LBM_EINVAL, "the persistent mode runs two steps per pass");
-  const int tx = l->tile_x ? l->tile_x : (fuse == 2 ? 256 : 64), ty = l->tile_y ? l->tile_y : (fuse == 2 ? 16 : 32);
+  // default row blocks: 16 rows for per-step launches; 24 for the persistent
+  // launch, where a taller tile spends fewer queue and barrier round trips per row
+  const int ty_default = fuse != 2 ? 32 : (l->mode == LBM_BATCH_PERSISTENT ? 24 : 16);
+  const int tx = l->tile_x ? l->tile_x : (fuse == 2 ? 256 : 64), ty = l->tile_y ? l->tile_y : ty_default;
   if (tx != 64 && tx != 128 && tx != 256) return fail(LBM_EINVAL, "tile_x %d not in {64,128,256}", tx);
   if (fuse == 2 && tx == 64) return fail(LBM_EINVAL, "tile_x 64 too narrow for two steps per launch");
   if (ty < 1) return fail(LBM_EINVAL, "tile_y %d < 1", ty);

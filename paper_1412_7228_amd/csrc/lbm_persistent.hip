@@ -128,10 +128,11 @@ __global__ void __launch_bounds__(BX, sizeof(T) == 4 ? 5 : 1)
     const BatchDomain<T>& D = dom[d];
     if (s > 0 && !wait_domain(done, d, D.ntiles * s, err, spin_limit, &s_flag)) break;
     const int p = (parity + (int)s) & 1;
+    // waves of a narrow strip with no needed lane only keep the barriers
     if (down)
-      step2_tile<T, EOS, BX, BIG, true>(D.f[p], D.f[p ^ 1], D.g, D.c, x0, y0, lds);
+      step2_tile<T, EOS, BX, BIG, true, true>(D.f[p], D.f[p ^ 1], D.g, D.c, x0, y0, lds);
     else
-      step2_tile<T, EOS, BX, BIG, false>(D.f[p], D.f[p ^ 1], D.g, D.c, x0, y0, lds);
+      step2_tile<T, EOS, BX, BIG, false, true>(D.f[p], D.f[p ^ 1], D.g, D.c, x0, y0, lds);
     // every wave's stores have reached this XCD's L2 before the tile is counted
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();

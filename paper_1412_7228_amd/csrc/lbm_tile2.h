@@ -25,6 +25,15 @@
 // the row behind three.  Lanes outside a stage's valid range compute on
 // whatever their neighbours hold (nothing of theirs is stored or read by a
 // valid lane), so control flow stays uniform.
+//
+// With SKIP, a wave none of whose lanes is needed (a strip narrower than the
+// workgroup, as narrow lattices and the last strip of a wide one are: W
+// stored columns need the first W + 6 lanes) runs only the barriers, as many
+// as the others pass (three per row), and nothing else.  The decision is
+// wave-uniform and taken once, so the stages of the busy waves stay one
+// straight-line block each.  It pays where a workgroup's freed issue slots go
+// to other work at once (the persistent batch kernel); in per-step launches
+// the idle waves computing their wrapped duplicate columns measure faster.
 #pragma once
 
 #include "lbm_tile.h"
@@ -44,7 +53,7 @@ struct Tile2Lds {
 template <int BX>
 constexpr int tile2_width() { return BX - 6; }
 
-template <typename T, int EOS, int BX, bool BIG, bool DOWN>
+template <typename T, int EOS, int BX, bool BIG, bool DOWN, bool SKIP = false>
 __device__ __forceinline__ void step2_tile(const T* __restrict__ fa, T* __restrict__ fb,
                                            const Geometry& geo, const DevC<T>& c, int xs, int y0,
                                            Tile2Lds<T, BX>& L) {
@@ -118,6 +127,18 @@ __device__ __forceinline__ void step2_tile(const T* __restrict__ fa, T* __restri
     Q[a] = T(0);
     R[a] = T(0);
     S[a] = T(0);
+  }
+  if constexpr (SKIP) {
+    const int W = min(tile2_width<BX>(), nx - xs);  // stored columns of this strip
+    if ((__builtin_amdgcn_readfirstlane(tx) & ~63) >= W + 6) {  // wave-uniform
+#pragma unroll 1
+      for (int i = 0; i < n; ++i) {
+        __syncthreads();
+        __syncthreads();
+        __syncthreads();
+      }
+      return;
+    }
   }
   gather_row(r0, P);
   const int l = tx + 1;

@@ -130,7 +130,7 @@ def test_batch_rejects_mixed_eos(lbm):
         lbm.Batch([dict(nx=16, ny=16, eos="cs"), dict(nx=16, ny=16, eos="vdw", K=0.3, T_over_Tc=0.9)])
 
 
-@pytest.mark.parametrize("tile", [(128, 16), (256, 8), (256, 16)])
+@pytest.mark.parametrize("tile", [(128, 16), (256, 8), (256, 16), (256, 24)])
 def test_persistent_many_domains_equals_per_step(lbm, tile):
     """48 uneven domains (several per XCD group), three calls (1, 99 and 200 steps: a
     single step alone, 49 pairs and a single step, 100 pairs): the persistent engine is
@@ -162,6 +162,16 @@ def test_persistent_many_domains_equals_per_step(lbm, tile):
         b.close()
     for i in range(len(cfgs)):
         assert np.array_equal(runs["persistent"][i], runs["per_step"][i], equal_nan=True), i
+
+
+def test_persistent_default_tile(lbm):
+    """The persistent mode's default row block is 24 rows (per-step: 16)."""
+    b = lbm.Batch([dict(nx=40, ny=30, eos="cs", precision="fp32")])
+    b.set_launch("persistent")
+    assert (b.launch["tile_x"], b.launch["tile_y"], b.launch["steps_per_pass"]) == (256, 24, 2)
+    b.set_launch("per_step")
+    assert (b.launch["tile_x"], b.launch["tile_y"], b.launch["steps_per_pass"]) == (256, 16, 2)
+    b.close()
 
 
 def test_persistent_mode_needs_two_steps_per_pass(lbm):

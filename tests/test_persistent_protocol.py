@@ -15,7 +15,13 @@ paper_1412_7228_amd/csrc/lbm_persistent.hip), before and besides its GPU tests.
   (s_andn2_b64 exec, exec, ...).  The fixture with that wait shape shows it;
   the library's persistent kernel, whose every loop test is on scalar values,
   must not, in any instantiation; and its one cache invalidation, after a
-  wait, is at agent scope."""
+  wait, is at agent scope.
+* The two-step kernels (lattice, per-step batch, persistent batch): a wave
+  must pass every barrier its workgroup passes.  In the assembly every
+  exec-masked region (the per-lane store guard) closes before any barrier or
+  branch, so all barriers sit in scalar control flow; the persistent kernel's
+  idle-wave path (waves of a narrow strip with no needed lane) is a loop of
+  three barriers per row, as many as the busy waves pass."""
 import os
 import re
 import shutil
@@ -102,3 +108,65 @@ def test_persistent_kernel_has_no_lane_dependent_loop(tmp_path):
         # buffer_inv sc0, leaves the L1 as it is outside thread-group-split mode)
         invs = [l.split()[1:] for l in body if l.strip().startswith("buffer_inv")]
         assert invs == [["sc1"]], (name, invs)
+
+
+def _masked_regions(body):
+    """Barriers reachable inside an exec-masked region: from each s_and_saveexec,
+    every path of the control flow (fall-through and branches) is followed until
+    the s_or_b64 exec restore of the same saved mask; a barrier met on the way
+    would be skipped by a wave whose mask is empty."""
+    lines = [l.strip() for l in body]
+    labels = {l.split(":")[0]: k for k, l in enumerate(lines) if l.startswith(".LBB")}
+    bad = []
+    for k, l in enumerate(lines):
+        m = re.match(r"s_and_saveexec_b64\s+(s\[\d+:\d+\])", l)
+        if not m:
+            continue
+        restore = "s_or_b64 exec, exec, " + m.group(1)
+        todo, seen = [k + 1], set()
+        while todo:
+            q = todo.pop()
+            while q < len(lines) and q not in seen:
+                seen.add(q)
+                t = lines[q]
+                if t.startswith(restore) or t.startswith("s_endpgm"):
+                    break
+                if t.startswith("s_barrier"):
+                    bad.append((k, q))
+                    break
+                if t.startswith("s_branch"):
+                    q = labels[t.split()[1]]
+                    continue
+                if t.startswith("s_cbranch"):
+                    todo.append(labels[t.split()[1]])
+                q += 1
+    return bad
+
+
+@pytest.mark.parametrize("src,prefix,count", [
+    ("lbm_step.hip", "_ZN3lbm7k_step2I", 32),
+    ("lbm_batch.hip", "_ZN3lbm13k_batch_step2I", 16),
+    ("lbm_persistent.hip", "_ZN3lbm18k_batch_persistentI", 16),
+])
+def test_two_step_kernels_reach_every_barrier_in_scalar_control_flow(tmp_path, src, prefix, count):
+    fns = _functions(_assembly(os.path.join(CSRC, src), tmp_path), prefix)
+    assert len(fns) == count
+    for name, body in fns.items():
+        assert sum("s_barrier" in l for l in body) >= 12, name  # 3 per row, 2 rows unrolled, 2 directions
+        assert _masked_regions(body) == [], name
+
+
+def test_persistent_idle_waves_pass_three_barriers_per_row(tmp_path):
+    fns = _functions(_assembly(os.path.join(CSRC, "lbm_persistent.hip"), tmp_path), "_ZN3lbm18k_batch_persistentI")
+    for name, body in fns.items():
+        ops = [l.split()[0] for l in (x.strip() for x in body) if l and not l.startswith((";", "."))]
+        triples = sum(1 for k in range(len(ops) - 2) if ops[k:k + 3] == ["s_barrier"] * 3)
+        assert triples >= 1, name
+
+
+def test_barrier_check_finds_a_barrier_in_a_divergent_branch(tmp_path):
+    fns = _functions(_assembly(os.path.join(PROTO, "barrier_in_branch.hip"), tmp_path), "_Z19k_barrier_in_branch")
+    assert len(fns) == 1
+    body = next(iter(fns.values()))
+    assert any("s_barrier" in l for l in body)
+    assert _masked_regions(body) != []
