@@ -54,9 +54,9 @@ FLOPS_PER_LU = 260  # FP arithmetic of one cell update in the single-step kernel
 # VALU issue utilisation of the same launches (SQ_INSTS_VALU against 256 CUs x
 # GRBM_GUI_ACTIVE / 8).  They hold for the kernel sources whose digest is
 # COUNTERS_SOURCE_DIGEST; for any other build they are reported as null.
-MEASURED_TRAFFIC = {("fp32", 256, 16): (780.1e6 + 619.1e6), ("fp64", 256, 69): (1347.9e6 + 1219.7e6)}
-MEASURED_VALU_ISSUE = {("fp32", 256, 16): 0.803, ("fp64", 256, 69): 0.451}
-COUNTERS_SOURCE_DIGEST = "b84783c6a719b218"
+MEASURED_TRAFFIC = {("fp32", 256, 16): (788.4e6 + 619.2e6), ("fp64", 256, 69): (1354.9e6 + 1219.9e6)}
+MEASURED_VALU_ISSUE = {("fp32", 256, 16): 0.804, ("fp64", 256, 69): 0.457}
+COUNTERS_SOURCE_DIGEST = "7bf19b368da828cb"
 KERNEL_SOURCES = ("lbm_device.h", "lbm_internal.h", "lbm_tile.h", "lbm_tile2.h", "lbm_step.hip")
 N = 4096
 RHO_MEAN = 0.183713  # (rho_v + rho_l)/2 of CS at 0.7Tc: (0.00929415 + 0.35813094)/2
