@@ -58,10 +58,18 @@ MEASURED_TRAFFIC = {("fp32", 256, 16): (788.4e6 + 619.2e6), ("fp64", 256, 69): (
 MEASURED_VALU_ISSUE = {("fp32", 256, 16): 0.804, ("fp64", 256, 69): 0.457}
 COUNTERS_SOURCE_DIGEST = "7bf19b368da828cb"
 KERNEL_SOURCES = ("lbm_device.h", "lbm_internal.h", "lbm_tile.h", "lbm_tile2.h", "lbm_step.hip")
-N = 4096
-RHO_MEAN = 0.183713  # (rho_v + rho_l)/2 of CS at 0.7Tc: (0.00929415 + 0.35813094)/2
-WORKLOAD = dict(nx=N, ny=N, eos="cs", T_over_Tc=0.7, A=-0.5, kappa=0.0)
-DROPLET_100 = dict(nx=100, ny=100, eos="cs", T_over_Tc=0.8, A=-0.5, kappa=0.0)
+from paper_1412_7228_amd import workloads  # noqa: E402  (data only: loads no library)
+
+# the throughput lattice and the end-to-end droplet (paper_1412_7228_amd/workloads.json)
+_LATTICE = workloads.get("lattice_4096_spinodal")
+N = _LATTICE["lattice"][0]
+RHO_MEAN = _LATTICE["rho_mean"]  # (rho_v + rho_l)/2 of CS at 0.7Tc
+SPINODAL_NOISE, SPINODAL_SEED = _LATTICE["noise"], _LATTICE["seed"]
+WORKLOAD = workloads.lattice_config("lattice_4096_spinodal")
+_DROP = workloads.get("droplet_100")
+DROPLET_100 = workloads.lattice_config("droplet_100")
+DROP_R, DROP_W, DROP_NOISE, DROP_SEED = (_DROP["droplet"][k] for k in ("R", "W", "noise", "seed"))
+DROP_STEPS = _DROP["steps"]
 BYTES_PER_LU = {"fp32": 72, "fp64": 144}
 
 
@@ -90,6 +98,7 @@ def parse():
     ap.add_argument("--no-slab", action="store_true", help="skip the one-GPU slab share measurement")
     ap.add_argument("--no-e2e", action="store_true", help="skip the end-to-end small workloads")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--log", default=None, help="append the result as one JSON line to this file (default: $LBM_RUN_LOG, unset = no log)")
     ap.add_argument("--tile", type=str, default="", help="tile_x,tile_y of the step kernel")
     ap.add_argument("--copy-mib", type=int, default=2048,
                     help="size of the device-to-device copy timed as the practical bandwidth ceiling "
@@ -161,7 +170,7 @@ def gpu_measure(precision, steps, warmup, tile):
     lat = lbm.Lattice(dict(WORKLOAD, precision=precision))
     if tile:
         lat.set_launch(*tile)
-    lat.init_field(inputs.spinodal(N, N, RHO_MEAN, noise=1e-2, seed=0))
+    lat.init_field(inputs.spinodal(N, N, RHO_MEAN, noise=SPINODAL_NOISE, seed=SPINODAL_SEED))
     spp = lat.launch[2]
     ms = time_steps(lat, steps, warmup)  # exactly `steps` (an odd count ends with one single step)
     ob = lat.observables(check=False)
@@ -222,7 +231,7 @@ def slab_share(launches=300, slabs=8, tiles=((0, 0), (256, 16), (256, 8), (128, 
 
     h, g = N // slabs, 4
     lat = lbm.Lattice(dict(WORKLOAD, ny=h + 2 * g, precision="fp32"))
-    rho = inputs.spinodal(N, h, RHO_MEAN, noise=1e-2, seed=0)
+    rho = inputs.spinodal(N, h, RHO_MEAN, noise=SPINODAL_NOISE, seed=SPINODAL_SEED)
     lat.init_field(np.concatenate([rho[-g:], rho, rho[:g]]))
     s = lat.stream
     ev = lambda: torch.cuda.Event(enable_timing=True)
@@ -292,19 +301,19 @@ def end_to_end():
 
     cfg = dict(DROPLET_100, precision="fp64")
     rv, rl = lbm.coexistence(cfg)
-    rho = inputs.droplet(100, 100, 25.0, rl, rv, W=5.0, noise=1e-3, seed=0)
+    rho = inputs.droplet(DROPLET_100["nx"], DROPLET_100["ny"], DROP_R, rl, rv, W=DROP_W, noise=DROP_NOISE, seed=DROP_SEED)
     torch.cuda.synchronize()
     t = time.perf_counter()
     lat = lbm.Lattice(cfg)
     lat.init_field(rho)
-    lat.step(5000)
+    lat.step(DROP_STEPS)
     ob_gpu = lat.observables()
     gpu_s = time.perf_counter() - t
     lat.close()
     # the benchmark lattice with its host transfers: initial density in (FP64, 134 MB),
     # 2000 steps, density field out (FP64)
     big = dict(WORKLOAD, precision="fp32")
-    rho_big = inputs.spinodal(N, N, RHO_MEAN, noise=1e-2, seed=0)
+    rho_big = inputs.spinodal(N, N, RHO_MEAN, noise=SPINODAL_NOISE, seed=SPINODAL_SEED)
     lat = lbm.Lattice(big)
     lat.init_field(rho_big)
     lat.step(20)
@@ -316,7 +325,7 @@ def end_to_end():
     out = lat.field("rho")
     io_s = time.perf_counter() - t
     lat.close()
-    cases = laplace.sweep_cases(extra_A=(-0.9, (0.6,)))
+    cases = laplace.full_sweep_cases()
     torch.cuda.synchronize()
     t = time.perf_counter()
     res = laplace.run_cases(cases, 20000, precision="fp32")
@@ -377,7 +386,7 @@ def cpu_baseline(seconds):
     host = host_cores()
     nthr = host["usable"]
     o = oracle.Oracle(WORKLOAD, nthreads=nthr)
-    o.init_field(inputs.spinodal(N, N, RHO_MEAN, noise=1e-2, seed=0))
+    o.init_field(inputs.spinodal(N, N, RHO_MEAN, noise=SPINODAL_NOISE, seed=SPINODAL_SEED))
     t = time.perf_counter()
     o.run(1)
     one = time.perf_counter() - t
@@ -392,12 +401,12 @@ def cpu_baseline(seconds):
     del o
     e = oracle.thermo.carnahan_starling()
     _, Tc = oracle.thermo.critical_point(e)
-    rv, rl = oracle.thermo.maxwell(e, 0.8 * Tc)
-    rho = inputs.droplet(100, 100, 25.0, rl, rv, W=5.0, noise=1e-3, seed=0)
+    rv, rl = oracle.thermo.maxwell(e, DROPLET_100["T_over_Tc"] * Tc)
+    rho = inputs.droplet(DROPLET_100["nx"], DROPLET_100["ny"], DROP_R, rl, rv, W=DROP_W, noise=DROP_NOISE, seed=DROP_SEED)
     t = time.perf_counter()
     d = oracle.Oracle(DROPLET_100, nthreads=nthr)
     d.init_field(rho)
-    d.run(5000)
+    d.run(DROP_STEPS)
     ob = d.observables()
     e2e_s = time.perf_counter() - t
     return dict(value=N * N * k / dt / 1e6, unit="MLUPS", cores=nthr, kind="oracle",
@@ -487,6 +496,9 @@ def main():
                     "hand-written copy kernel and torch's copy"},
     }
     print(json.dumps(line), flush=True)
+    from paper_1412_7228_amd import runlog
+
+    runlog.append(dict(kind="bench", result=line), a.log)
 
 
 if __name__ == "__main__":

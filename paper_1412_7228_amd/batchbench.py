@@ -24,7 +24,7 @@ import time
 
 import numpy as np
 
-from . import autotune, inputs, laplace, lbm
+from . import autotune, inputs, laplace, lbm, runlog, workloads
 
 
 def build(domains: int, seed: int, precision: str = "fp32", screen: bool = True,
@@ -68,14 +68,16 @@ def time_mode(b, mode, tile, steps, steps_per_pass=1):
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("--steps", type=int, default=20000)
-    ap.add_argument("--domains", type=int, default=256)
-    ap.add_argument("--seed", type=int, default=3)
+    w = workloads.get("uneven_batch_256")
+    ap.add_argument("--steps", type=int, default=w["steps"])
+    ap.add_argument("--domains", type=int, default=w["domains"])
+    ap.add_argument("--seed", type=int, default=w["seed"])
     ap.add_argument("--tune", action="store_true", help="run the autotuner first")
     ap.add_argument("--no-screen", action="store_true", help="keep infeasible draws (no redraw)")
     ap.add_argument("--max-ratio", type=float, default=laplace.SCREEN_MAX_RATIO,
                     help="screen: largest flat density ratio kept (0: no cap)")
     ap.add_argument("--modes", default="1,2x128,2x256,p256", help="launch modes to time")
+    ap.add_argument("--log", default=None, help="append the result as one JSON line to this file (default: $LBM_RUN_LOG, unset = no log)")
     ap.add_argument("--save-draws", default=None, help="write the (screened) draws to this JSON file")
     ap.add_argument("--load-draws", default=None,
                     help="take the draws from a file written by --save-draws (no screen run; for profiling)")
@@ -121,6 +123,7 @@ def main():
                                                              rejected=report["rejected"]),
                 autotune=tuned, seconds=time.time() - t0)
     print(json.dumps(line), flush=True)
+    runlog.append(dict(kind="batchbench", result=line), a.log)
 
 
 if __name__ == "__main__":

@@ -84,10 +84,25 @@ def taylor_green(n: int, u0: float = 0.01, rho0: float = 1.0, modes: int = 1):
     return np.full((n, n), rho0), ux, uy
 
 
-def batch_draw_stream(seed: int, side=(64, 512), r_frac=(0.15, 0.35), t_over_tc=(0.6, 0.85),
-                      kappa=(0.0, 0.8), A=(-0.7, -0.3)):
+def batch_ranges() -> dict:
+    """The uneven batch's draw ranges (workloads.json, ``uneven_batch_256``)."""
+    from . import workloads
+
+    w = workloads.get("uneven_batch_256")
+    return dict(side=tuple(w["side"]), r_frac=tuple(w["r_frac"]), t_over_tc=tuple(w["T_over_Tc"]),
+                kappa=tuple(w["kappa"]), A=tuple(w["A"]))
+
+
+def batch_draw_stream(seed: int, side=None, r_frac=None, t_over_tc=None, kappa=None, A=None):
     """Endless seeded stream of independent draws of the uneven droplet batch, one dict per
-    domain (``index`` counts the draws of the stream)."""
+    domain (``index`` counts the draws of the stream); a range left None is the
+    workload's (:func:`batch_ranges`)."""
+    d = batch_ranges()
+    side = side or d["side"]
+    r_frac = r_frac or d["r_frac"]
+    t_over_tc = t_over_tc or d["t_over_tc"]
+    kappa = kappa or d["kappa"]
+    A = A or d["A"]
     g = rng(seed)
     i = 0
     while True:
@@ -101,8 +116,8 @@ def batch_draw_stream(seed: int, side=(64, 512), r_frac=(0.15, 0.35), t_over_tc=
         i += 1
 
 
-def batch_draws(n: int, seed: int, side=(64, 512), r_frac=(0.15, 0.35), t_over_tc=(0.6, 0.85),
-                kappa=(0.0, 0.8), A=(-0.7, -0.3)) -> list[dict]:
+def batch_draws(n: int, seed: int, side=None, r_frac=None, t_over_tc=None, kappa=None,
+                A=None) -> list[dict]:
     """The first n draws of :func:`batch_draw_stream` (no feasibility screen)."""
     stream = batch_draw_stream(seed, side, r_frac, t_over_tc, kappa, A)
     return [next(stream) for _ in range(n)]

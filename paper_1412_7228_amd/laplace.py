@@ -26,7 +26,10 @@ import itertools
 
 import numpy as np
 
-from . import inputs, lbm
+from . import inputs, lbm, workloads
+
+_SWEEP = workloads.get("laplace_sweep_200")
+_SCREEN = workloads.get("uneven_batch_256")["feasibility"]
 
 
 def case_config(case: dict, precision: str = "fp32") -> dict:
@@ -78,8 +81,9 @@ def laplace_sigma(results: list) -> tuple[float, float]:
     return lbm.laplace_fit([r["dp"] for r in results], [r["R_e"] for r in results])
 
 
-def sweep_cases(radii=(20, 30, 40, 50, 60), temps=(0.6, 0.7, 0.8), kappas=(0.0, 0.3, 0.6),
-                A: float = -0.5, n: int = 200, extra_A=None) -> list:
+def sweep_cases(radii=tuple(_SWEEP["radii"]), temps=tuple(_SWEEP["T_over_Tc"]),
+                kappas=tuple(_SWEEP["kappa"]), A: float = _SWEEP["A"], n: int = _SWEEP["lattice"][0],
+                extra_A=None) -> list:
     """The Laplace sweep: one droplet per (R, T/Tc, kappa) on an n x n lattice; with
     ``extra_A`` = (A', temps') also the rows (A', T) for T in temps'."""
     cases = []
@@ -96,12 +100,19 @@ def sweep_cases(radii=(20, 30, 40, 50, 60), temps=(0.6, 0.7, 0.8), kappas=(0.0, 
     return cases
 
 
-SCREEN_SLAB = (64, 4)      # flat slab: 64 cells across two interfaces, 4 rows
-SCREEN_STEPS = 20000
-SCREEN_MIN_RATIO = 2.0     # rho_max / rho_min that still counts as two phases
+def full_sweep_cases() -> list:
+    """The whole Laplace sweep workload: the (R, T/Tc, kappa) grid at its A and the extra
+    rows at the other A (60 drops on 200 x 200)."""
+    extra = _SWEEP["extra_rows"]
+    return sweep_cases(extra_A=(extra["A"], tuple(extra["T_over_Tc"])))
+
+
+SCREEN_SLAB = tuple(_SCREEN["slab"])     # flat slab: 64 cells across two interfaces, 4 rows
+SCREEN_STEPS = _SCREEN["steps"]
+SCREEN_MIN_RATIO = _SCREEN["min_ratio"]  # rho_max / rho_min that still counts as two phases
 # largest flat density ratio kept: draws whose gas sinks towards zero (ratios of 10^4
 # and more after the screen) hold on the slab for a while but fault as droplets
-SCREEN_MAX_RATIO = 1000.0
+SCREEN_MAX_RATIO = _SCREEN["max_ratio"]
 
 
 def screen_flat(cases: list, steps: int = SCREEN_STEPS, precision: str = "fp32",

@@ -35,7 +35,7 @@ import time
 
 import numpy as np
 
-from . import inputs, laplace, lbm, oscillation
+from . import inputs, laplace, lbm, oscillation, runlog
 
 VDW_SEC3 = dict(eos="vdw", K=0.3)                  # Sec. 3: vdW with K = 0.3
 PR_SEC4 = dict(eos="pr", K=0.5, T_over_Tc=0.8, A=-0.3)  # Sec. 4
@@ -70,7 +70,7 @@ def stable(o: dict, max_u: float = 0.1) -> bool:
 
 # ---------------------------------------------------------------------------
 def laplace_sweep(steps: int = 20000, precision: str = "fp32") -> dict:
-    cases = laplace.sweep_cases(extra_A=(-0.9, (0.6,)))
+    cases = laplace.full_sweep_cases()
     res = laplace.run_cases(cases, steps, precision=precision, tile=(128, 16))
     groups = {}
     for r in res:
@@ -242,6 +242,7 @@ def main():
     ap.add_argument("study", choices=sorted(STUDIES) + ["all"])
     ap.add_argument("--out", default=None, help="JSON report (default <study>.json)")
     ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--log", default=None, help="append the result as one JSON line to this file (default: $LBM_RUN_LOG, unset = no log)")
     a = ap.parse_args()
     names = sorted(STUDIES) if a.study == "all" else [a.study]
     reports = {}
@@ -252,6 +253,7 @@ def main():
         rep["seconds"] = time.time() - t0
         reports[name] = rep
         print(f"[study] {name} done in {rep['seconds']:.1f} s", flush=True)
+        runlog.append(dict(kind=f"study:{name}", result=rep), a.log)
     out = a.out or f"{a.study}.json"
     with open(out, "w") as f:
         json.dump(reports if a.study == "all" else reports[a.study], f, indent=1)

@@ -33,12 +33,18 @@ import time
 
 import numpy as np
 
-from . import inputs, laplace, lbm
+from . import inputs, laplace, lbm, runlog, workloads
+
+_STUDY = workloads.get("surrogate_sigma_targets")
+_RANGES = inputs.batch_ranges()  # targets' (A, T/Tc) come from the training distribution
+VERIFY_N = _STUDY["verify"]["lattice"][0]
+VERIFY_R = _STUDY["verify"]["R"]
+VERIFY_STEPS = _STUDY["verify"]["steps"]
 
 FEATURE_LO = np.array([-0.7, 0.0, 0.6])   # A, kappa, T/Tc
 FEATURE_HI = np.array([-0.3, 0.8, 0.85])
 KAPPA_RANGE = (0.0, 0.8)
-TOLERANCE = 0.02
+TOLERANCE = _STUDY["tolerance"]
 
 
 def features(A, kappa, T) -> np.ndarray:
@@ -185,7 +191,7 @@ def training_set(n_batches: int, seed: int, steps: int, side=(64, 512), domains:
     return np.array(X), np.array(Y), bad, sized, cost
 
 
-def training_set_fixed(n_batches: int, seed: int, steps: int, n: int = 200, R: float = 40.0,
+def training_set_fixed(n_batches: int, seed: int, steps: int, n: int = VERIFY_N, R: float = VERIFY_R,
                        domains: int = 256, log=print):
     """Droplets of one geometry (n x n lattice, initial radius R) with (T/Tc, kappa, A)
     drawn from the uneven batch's ranges (feasible draws), run in batches of `domains`;
@@ -212,7 +218,7 @@ def training_set_fixed(n_batches: int, seed: int, steps: int, n: int = 200, R: f
     return np.array(X), np.array(Y), bad, cost
 
 
-def verify(specs, steps: int, n: int = 200, R: float = 40.0):
+def verify(specs, steps: int, n: int = VERIFY_N, R: float = VERIFY_R):
     """One LBM droplet run per (A, kappa, T/Tc) spec; returns sigma (nan if the run failed)."""
     cases = [dict(n=n, R=R, A=a, kappa=k, T_over_Tc=t, seed=i) for i, (a, k, t) in enumerate(specs)]
     res = laplace.run_cases(cases, steps, precision="fp32")
@@ -227,7 +233,7 @@ def run_accounting(cost: dict, n_targets: int, verify_steps: int, baselines: dic
     study's targets, the surrogate's cost per target is its own runs plus training runs /
     targets, and the network pays off once the targets outnumber training runs / (baseline
     runs - surrogate runs)."""
-    unit = 200 * 200 * verify_steps
+    unit = VERIFY_N * VERIFY_N * verify_steps
     train_runs = cost["runs"]
     train_units = (cost["updates"] + cost["screen_updates"]) / unit
     out = dict(training_runs=train_runs, training_updates_in_verify_runs=round(train_units, 1),
@@ -253,8 +259,9 @@ def _num(x):
     return float(x) if np.isfinite(x) else None
 
 
-def study(seed: int = 0, n_targets: int = 64, train_batches: int = 4, train_steps: int = 60000,
-          verify_steps: int = 20000, side=(64, 512), domains: int = 256, iters: int = 20000,
+def study(seed: int = 0, n_targets: int = _STUDY["targets"], train_batches: int = _STUDY["train"]["batches"],
+          train_steps: int = _STUDY["train"]["steps"], verify_steps: int = VERIFY_STEPS,
+          side=_RANGES["side"], domains: int = _STUDY["train"]["domains"], iters: int = 20000,
           lr: float = 1e-3, train_geometry: str = "uneven", cosine: bool = True, log=print) -> dict:
     """The whole comparison.  ``train_geometry`` "uneven": training droplets as in the
     uneven batch (`side`, R = u * side, `train_steps` steps); "verify": every training
@@ -265,7 +272,7 @@ def study(seed: int = 0, n_targets: int = 64, train_batches: int = 4, train_step
                                               domains=domains, log=log)
     elif train_geometry == "verify":
         X, Y, bad, cost = training_set_fixed(train_batches, seed, verify_steps, domains=domains, log=log)
-        sized, train_steps, side = 0, verify_steps, (200, 200)
+        sized, train_steps, side = 0, verify_steps, (VERIFY_N, VERIFY_N)
     else:
         raise ValueError(f"unknown training geometry {train_geometry!r}")
     t_trained = time.time()
@@ -278,9 +285,10 @@ def study(seed: int = 0, n_targets: int = 64, train_batches: int = 4, train_step
             f"{h['train'][-1]:.3e}, held-out best {h['best_val']} at step {h['best_iter']}")
     # targets: (A, T/Tc) from the training distribution; sigma* = s sigma_0, s log-uniform in [0.2, 1]
     g = inputs.rng(seed + 1000)
-    A = g.uniform(-0.7, -0.3, n_targets)
-    T = g.uniform(0.6, 0.85, n_targets)
-    s = np.exp(g.uniform(math.log(0.2), 0.0, n_targets))
+    A = g.uniform(*_RANGES["A"], n_targets)
+    T = g.uniform(*_RANGES["t_over_tc"], n_targets)
+    lo, hi = _STUDY["target_scale"]
+    s = np.exp(g.uniform(math.log(lo), math.log(hi), n_targets))
     sigma0 = verify([(a, 0.0, t) for a, t in zip(A, T)], verify_steps)
     valid = np.isfinite(sigma0) & (sigma0 > 0)
     target = s * sigma0
@@ -384,7 +392,7 @@ def study(seed: int = 0, n_targets: int = 64, train_batches: int = 4, train_step
         accounting=accounting,
         config=dict(seed=seed, n_targets=n_targets, train_batches=train_batches, domains=domains,
                     train_geometry=train_geometry, train_steps=train_steps, verify_steps=verify_steps,
-                    side=list(side), verify_lattice=200, verify_radius=40, tolerance=TOLERANCE,
+                    side=list(side), verify_lattice=VERIFY_N, verify_radius=VERIFY_R, tolerance=TOLERANCE,
                     iters=iters, lr=lr, cosine=cosine),
         training=dict(samples=int(len(X)), outside_model_range=int(bad), left_out_for_radius=int(sized),
                       X=X.tolist(), Y=Y.tolist()),
@@ -404,17 +412,18 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--out", default="surrogate_report.json")
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--targets", type=int, default=64)
-    ap.add_argument("--train-batches", type=int, default=4)
-    ap.add_argument("--train-steps", type=int, default=60000,
+    ap.add_argument("--targets", type=int, default=_STUDY["targets"])
+    ap.add_argument("--train-batches", type=int, default=_STUDY["train"]["batches"])
+    ap.add_argument("--train-steps", type=int, default=_STUDY["train"]["steps"],
                     help="steps of the training droplets (large drops relax slowly)")
-    ap.add_argument("--verify-steps", type=int, default=20000)
+    ap.add_argument("--verify-steps", type=int, default=VERIFY_STEPS)
     ap.add_argument("--iters", type=int, default=20000)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--constant-lr", action="store_true",
                     help="keep the step size constant (default: cosine decay to lr / 100)")
     ap.add_argument("--train-geometry", choices=("uneven", "verify"), default="uneven",
                     help="training droplets as in the uneven batch, or all on the verification geometry")
+    ap.add_argument("--log", default=None, help="append the result as one JSON line to this file (default: $LBM_RUN_LOG, unset = no log)")
     a = ap.parse_args()
     rep = study(seed=a.seed, n_targets=a.targets, train_batches=a.train_batches,
                 train_steps=a.train_steps, verify_steps=a.verify_steps, iters=a.iters, lr=a.lr,
@@ -423,6 +432,7 @@ def main():
     with open(a.out, "w") as f:
         json.dump(rep, f, indent=1)
     print(json.dumps(rep), flush=True)
+    runlog.append(dict(kind="surrogate", result=rep), a.log)
 
 
 if __name__ == "__main__":

@@ -26,14 +26,17 @@ ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__)
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-N = 200
-RADII = (20, 30, 40, 50, 60)
-TEMPS = (0.6, 0.7, 0.8)
-KAPPAS = (0.0, 0.3, 0.6)
-A_MAIN = -0.5
-A_EXTRA, TEMPS_EXTRA = -0.9, (0.6,)
-CHECKPOINTS = (5000, 10000, 15000, 20000)
-W, NOISE = 5.0, 1e-3
+from paper_1412_7228_amd import workloads  # noqa: E402  (the sweep's grid, as data)
+
+_SWEEP = workloads.get("laplace_sweep_200")
+N = _SWEEP["lattice"][0]
+RADII = tuple(_SWEEP["radii"])
+TEMPS = tuple(_SWEEP["T_over_Tc"])
+KAPPAS = tuple(_SWEEP["kappa"])
+A_MAIN = _SWEEP["A"]
+A_EXTRA, TEMPS_EXTRA = _SWEEP["extra_rows"]["A"], tuple(_SWEEP["extra_rows"]["T_over_Tc"])
+CHECKPOINTS = tuple(_SWEEP["checkpoints"])
+W, NOISE = _SWEEP["droplet"]["W"], _SWEEP["droplet"]["noise"]
 OBS_KEYS = ("mass", "mom_x", "mom_y", "rho_min", "rho_max", "rho_in", "rho_out", "p_in", "p_out",
             "dp", "R_e", "sigma", "max_u", "n_domain", "n_nonfinite")
 
