@@ -155,3 +155,20 @@ def test_library_laplace_fit_matches_oracle(lib, oracle_mod):
                           ([1e-3], [float("inf")])):
         with pytest.raises(lbm.LBMError):
             lbm.laplace_fit(bad_dp, bad_r)
+
+
+def test_batch_arguments_are_rejected_before_device_use(lib):
+    """An empty batch, a NULL parameter array, mixed EOS kinds or precisions and an
+    invalid domain are refused on the host, before any device call."""
+    good = lbm.make_params(dict(nx=16, ny=16, eos="cs", precision="fp32"))
+    arr = (lbm.Params * 3)(good, good, good)
+    h = ctypes.c_void_p()
+    assert lib.lbm_batch_create(arr, 0, None, ctypes.byref(h)) == -1
+    assert lib.lbm_batch_create(None, 3, None, ctypes.byref(h)) == -1
+    for other in (dict(nx=16, ny=16, eos="vdw", K=0.3, T_over_Tc=0.9, precision="fp32"),
+                  dict(nx=16, ny=16, eos="cs", precision="fp64"),
+                  dict(nx=2, ny=16, eos="cs", precision="fp32")):
+        arr[1] = lbm.make_params(other)
+        assert lib.lbm_batch_create(arr, 3, None, ctypes.byref(h)) == -1
+        assert not h.value
+        assert b"batch" in lib.lbm_last_error()
