@@ -16,8 +16,8 @@ import os
 LATTICE_CANDIDATES = [(256, 16, 1), (256, 64, 1), (128, 32, 1), (64, 32, 1),
                       (256, 8, 2), (256, 12, 2), (256, 16, 2), (256, 20, 2), (256, 24, 2), (256, 32, 2),
                       (128, 8, 2), (128, 16, 2), (128, 32, 2), (128, 64, 2)]
-# (mode, tile_x, tile_y, steps_per_pass); the persistent mode is switched off in
-# the library for now
+# (mode, tile_x, tile_y, steps_per_pass): per-step launches (one or two steps per
+# launch) and the persistent launch (two steps per pass)
 BATCH_CANDIDATES = [("per_step", 64, 16, 1), ("per_step", 64, 32, 1), ("per_step", 128, 16, 1),
                     ("per_step", 128, 8, 2), ("per_step", 128, 16, 2), ("per_step", 128, 32, 2),
                     ("per_step", 256, 8, 2), ("per_step", 256, 16, 2), ("per_step", 256, 32, 2),
