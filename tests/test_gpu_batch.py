@@ -217,8 +217,9 @@ def test_full_size_uneven_batch_sampled_domains(lbm, oracle_mod):
     lowest temperature at which the method holds two phases for their A, Sec. 3.1.2, are
     redrawn), so no domain may fault; every domain keeps its mass, five sampled domains
     (the smallest, the largest and three drawn) are bitwise the same lattice run alone,
-    and the smallest domain matches the FP64 oracle.  Densities start from the oracle's
-    Maxwell construction for each draw."""
+    and the smallest domain matches the FP64 oracle; then the same 201 steps in the
+    persistent launch give every domain bitwise the per-step state.  Densities start from
+    the oracle's Maxwell construction for each draw."""
     from paper_1412_7228_amd import laplace
 
     say("uneven batch: feasibility screen of the draw stream")
@@ -273,6 +274,18 @@ def test_full_size_uneven_batch_sampled_domains(lbm, oracle_mod):
     want = o.fields()["rho"]
     got = b.field(small, "rho")
     assert float(np.abs(got - want).max() / np.abs(want).max()) < 1e-5
+    # the same batch in the persistent launch (its default 256 x 24 tiles, 100 pairs in one
+    # launch and a single step): every domain bitwise the per-step result
+    say("  persistent launch, all 256 domains against the per-step run")
+    per_step = [b.f_soa(i) for i in range(256)]
+    b.set_launch("persistent")
+    assert (b.launch["mode"], b.launch["tile_y"]) == ("persistent", 24)
+    for i, r in enumerate(rhos):
+        b.init_field(i, r)
+    b.step(steps)
+    assert all(o["step"] == 2 * steps for o in b.observables())  # the batch's clock runs on
+    differ = [i for i in range(256) if not np.array_equal(b.f_soa(i), per_step[i], equal_nan=True)]
+    assert differ == [], differ
     b.close()
 
 
