@@ -258,8 +258,8 @@ lbm_status validate(const lbm_params* p) {
   if (p->precision != LBM_FP64 && p->precision != LBM_FP32)
     return fail(LBM_EINVAL, "unknown precision %d", p->precision);
   // one distribution plane must stay below 4 GiB (32-bit buffer offsets)
-  const unsigned long long plane_bytes = (unsigned long long)p->ny * ((p->nx + 63) / 64 * 64) *
-                                         (p->precision == LBM_FP32 ? 4u : 8u);
+  const unsigned long long plane_bytes =
+      ((unsigned long long)p->ny * ((p->nx + 63) / 64 * 64) + LBM_PLANE_GAP) * (p->precision == LBM_FP32 ? 4u : 8u);
   if (plane_bytes >= (1ull << 32))
     return fail(LBM_EINVAL, "lattice %d x %d too large: one plane is %llu bytes (limit 4 GiB)",
                 p->nx, p->ny, plane_bytes);
@@ -290,6 +290,10 @@ uint64_t params_hash(const lbm_params& p) {
 }
 
 int pitch_of(const lbm_params& p) { return (p.nx + 63) / 64 * 64; }
+
+// Elements from one plane to the next: the rows and the gap that staggers the
+// planes across HBM channels (LBM_PLANE_GAP, in lbm.h).
+long long plane_of(const lbm_params& p) { return (long long)p.ny * pitch_of(p) + LBM_PLANE_GAP; }
 
 size_t elem_size(const lbm_params& p) { return p.precision == LBM_FP32 ? 4 : 8; }
 
@@ -332,7 +336,7 @@ Geometry make_geometry(const lbm_params& p, int tile_x, int tile_y, int width) {
   g.nx = p.nx;
   g.ny = p.ny;
   g.pitch = pitch_of(p);
-  g.plane = (long long)g.ny * g.pitch;
+  g.plane = plane_of(p);
   g.tile_x = tile_x;
   g.tile_y = tile_y;
   g.nstrips = (g.nx + width - 1) / width;
@@ -475,7 +479,7 @@ lbm_status make_ctx(const lbm_params* p, void* stream, void* ba, void* bb, size_
       }
     }
   }
-  // zero both buffers so the pitch padding is defined
+  // zero both buffers so the pitch padding and the gaps between planes are defined
   for (int i = 0; i < 2; ++i) {
     hipError_t e = hipMemsetAsync(c->buf[i], 0, c->buf_bytes, c->stream);
     if (e != hipSuccess) { lbm_destroy(c); return fail(LBM_EDEVICE, "hipMemsetAsync: %s", hipGetErrorString(e)); }
@@ -657,7 +661,7 @@ lbm_status lbm_laplace_fit(const double* dp, const double* R_e, int32_t n, doubl
 
 size_t lbm_buffer_bytes(const lbm_params* p) {
   if (validate(p) != LBM_OK) return 0;
-  return 9 * (size_t)p->ny * pitch_of(*p) * elem_size(*p);
+  return 9 * (size_t)plane_of(*p) * elem_size(*p);
 }
 
 lbm_status lbm_create(const lbm_params* p, void* hip_stream, lbm_ctx** out) {
@@ -1254,7 +1258,7 @@ lbm_status lbm_batch_create(const lbm_params* params, int32_t n, void* hip_strea
     g.y_begin = 0;
     g.y_end = g.ny;
     g.pitch = pitch_of(params[d]);
-    g.plane = (long long)g.ny * g.pitch;
+    g.plane = plane_of(params[d]);
     const size_t bytes = (9 * (size_t)g.plane * es + 255) / 256 * 256;
     if (9 * (size_t)g.plane * es >= (1ull << 32)) {
       lbm_batch_destroy(b);
