@@ -99,6 +99,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-slab", action="store_true", help="skip the one-GPU slab share measurement")
     ap.add_argument("--no-e2e", action="store_true", help="skip the end-to-end small workloads")
+    ap.add_argument("--no-batch", action="store_true", help="skip the uneven droplet batch")
+    ap.add_argument("--batch-steps", type=int, default=200, help="timed steps per batch launch mode")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--log", default=None, help="append the result as one JSON line to this file (default: $LBM_RUN_LOG, unset = no log)")
     ap.add_argument("--tile", type=str, default="", help="tile_x,tile_y of the step kernel")
@@ -342,6 +344,28 @@ def end_to_end():
                     rho_finite=bool(np.isfinite(out).all())))
 
 
+def uneven_batch(steps):
+    """The uneven droplet batch (256 screened draws of the seeded stream, sides 64-512,
+    about 25 M cells, FP32) in its two launch modes, timed with HIP events on the batch's
+    stream after 10 untimed steps: per-step launches (256 x 16 tiles) and the persistent
+    launch (its default 256 x 24 tiles).  Not the benchmark's value: the same kernel over
+    uneven domains."""
+    from paper_1412_7228_amd import batchbench, workloads
+
+    w = workloads.get("uneven_batch_256")
+    b, cases, cells, report = batchbench.build(w["domains"], w["seed"])
+    modes = {}
+    for mode, tile in (("per_step", (256, 16)), ("persistent", (256, 24))):
+        ms = batchbench.time_mode(b, mode, tile, steps, steps_per_pass=2)
+        modes[f"{mode}_{tile[0]}x{tile[1]}"] = dict(mlups=round(cells * steps / (ms * 1e-3) / 1e6, 1),
+                                                    ms=round(ms, 3))
+    obs = b.observables(check=False)
+    b.close()
+    return dict(domains=len(cases), cells=cells, timed_steps_per_mode=steps, modes=modes,
+                redraws=report["redraws"] if report else None,
+                domains_with_faults=sum(1 for o in obs if o["n_nonfinite"] > 0 or o["n_domain"] > 0))
+
+
 def host_cores() -> dict:
     """The host's CPUs as this process sees them: nproc, the CPUs it may run on, the
     cgroup CPU quota, the CPU model; `usable` = the threads the oracle runs on."""
@@ -449,6 +473,11 @@ def main():
         print("[bench] end-to-end workloads", file=sys.stderr, flush=True)
         e2e = end_to_end()
         print(f"[bench] end-to-end {e2e}", file=sys.stderr, flush=True)
+    batch = None
+    if not a.no_batch:
+        print("[bench] uneven droplet batch", file=sys.stderr, flush=True)
+        batch = uneven_batch(a.batch_steps)
+        print(f"[bench] batch {batch}", file=sys.stderr, flush=True)
     copy = None
     if a.copy_mib > 0:
         copy = copy_bandwidth(a.copy_mib)
@@ -486,6 +515,7 @@ def main():
         },
         "slab_share": slab,
         "end_to_end": e2e,
+        "uneven_batch": batch,
         "cpu_baseline": cpu,
         "copy_ceiling": None if copy is None else {
             "gbs": copy["gbs"], "bytes": copy["bytes_per_copy"], "kernels": copy["kernels"],

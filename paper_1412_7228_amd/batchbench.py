@@ -28,11 +28,11 @@ from . import autotune, inputs, laplace, lbm, runlog, workloads
 
 
 def build(domains: int, seed: int, precision: str = "fp32", screen: bool = True,
-          max_ratio: float | None = None, draws_file: str | None = None):
+          max_ratio: float | None = laplace.SCREEN_MAX_RATIO, draws_file: str | None = None):
     """The batch of `domains` droplets from the seeded draw stream: the first feasible
-    draws (laplace.feasible_batch_draws) unless screen is False, or the draws (and screen
-    report) stored in `draws_file` by an earlier run.  Returns (batch, cases, cells,
-    screen report)."""
+    draws (laplace.feasible_batch_draws, density-ratio cap `max_ratio`, None for none)
+    unless screen is False, or the draws (and screen report) stored in `draws_file` by an
+    earlier run.  Returns (batch, cases, cells, screen report)."""
     if draws_file:
         with open(draws_file) as fh:
             saved = json.load(fh)

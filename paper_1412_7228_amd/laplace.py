@@ -120,8 +120,8 @@ def screen_flat(cases: list, steps: int = SCREEN_STEPS, precision: str = "fp32",
     """Runs each case's (T/Tc, A, kappa, EOS) on a thin periodic flat slab (a liquid layer
     between the library's Maxwell densities) on the batched engine for `steps` steps.
     Returns one dict per case: ``ok`` (finite, positive, no U > 0 cell, rho_max / rho_min
-    >= SCREEN_MIN_RATIO), the slab's liquid and gas densities and their ratio, and the
-    reason when not ok."""
+    >= SCREEN_MIN_RATIO, and at most max_ratio unless that is None), the slab's liquid and
+    gas densities and their ratio, and the reason when not ok."""
     nx, ny = SCREEN_SLAB
     cfgs = []
     for c in cases:

@@ -91,3 +91,14 @@ def test_run_log(tmp_path, monkeypatch):
     for l in lines:
         assert {"time", "host", "argv", "library", "kind", "result"} <= set(l)
         assert l["host"]["cpus"] == os.cpu_count()
+
+
+def test_batch_build_screens_with_the_ratio_cap_by_default():
+    """batchbench.build (used by the batch benchmark and bench.py) screens the draw stream
+    with the workload's density-ratio cap unless told otherwise."""
+    import inspect
+
+    from paper_1412_7228_amd import batchbench
+
+    assert inspect.signature(batchbench.build).parameters["max_ratio"].default == laplace.SCREEN_MAX_RATIO == 1000.0
+    assert inspect.signature(laplace.feasible_batch_draws).parameters["max_ratio"].default == 1000.0
