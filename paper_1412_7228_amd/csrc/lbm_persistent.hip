@@ -100,8 +100,9 @@ __device__ __forceinline__ bool wait_domain(unsigned* done, int d, unsigned targ
   return ok;
 }
 
+// Gathers two rows ahead (AHEAD = 2 of step2_tile); FP32: four waves per SIMD.
 template <typename T, int EOS, int BX, bool BIG>
-__global__ void __launch_bounds__(BX, sizeof(T) == 4 ? 5 : 1)
+__global__ void __launch_bounds__(BX, sizeof(T) == 4 ? 4 : 1)
     k_batch_persistent(const BatchDomain<T>* __restrict__ dom, const BatchTile* __restrict__ tiles,
                        const int* __restrict__ group_begin, int ngroups, unsigned* __restrict__ head,
                        unsigned* __restrict__ done, int* __restrict__ err, int npairs, int parity,
@@ -130,9 +131,9 @@ __global__ void __launch_bounds__(BX, sizeof(T) == 4 ? 5 : 1)
     const int p = (parity + (int)s) & 1;
     // waves of a narrow strip with no needed lane only keep the barriers
     if (down)
-      step2_tile<T, EOS, BX, BIG, true, true>(D.f[p], D.f[p ^ 1], D.g, D.c, x0, y0, lds);
+      step2_tile<T, EOS, BX, BIG, true, true, 2>(D.f[p], D.f[p ^ 1], D.g, D.c, x0, y0, lds);
     else
-      step2_tile<T, EOS, BX, BIG, false, true>(D.f[p], D.f[p ^ 1], D.g, D.c, x0, y0, lds);
+      step2_tile<T, EOS, BX, BIG, false, true, 2>(D.f[p], D.f[p ^ 1], D.g, D.c, x0, y0, lds);
     // every wave's stores have reached this XCD's L2 before the tile is counted
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();

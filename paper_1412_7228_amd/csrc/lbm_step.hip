@@ -63,10 +63,10 @@ static hipError_t launch_step_p(const Geometry& g, const ModelConsts& m, const v
 }
 
 // Two fused steps over the whole lattice; the same workgroup-to-tile order.
-// FP32: at most 102 VGPRs, so that 5 workgroups of 256 lanes (31 KB of LDS
-// each) fit on a CU.
+// Gathers two rows ahead (AHEAD = 2 of step2_tile); FP32: at most 128 VGPRs,
+// four waves per SIMD.
 template <typename T, int EOS, int BX, bool BIG>
-__global__ void __launch_bounds__(BX, sizeof(T) == 4 ? 5 : 1) k_step2(const T* __restrict__ fa, T* __restrict__ fb,
+__global__ void __launch_bounds__(BX, sizeof(T) == 4 ? 4 : 1) k_step2(const T* __restrict__ fa, T* __restrict__ fb,
                                                const Geometry geo, const DevC<T> c) {
   __shared__ Tile2Lds<T, BX> lds;
   static_assert(tile2_width<BX>() == BX - kStep2Halo, "strip width");
@@ -75,9 +75,9 @@ __global__ void __launch_bounds__(BX, sizeof(T) == 4 ? 5 : 1) k_step2(const T* _
   const int strip = lb - rb * geo.nstrips;
   const int xs = strip * tile2_width<BX>(), y0 = geo.y_begin + rb * geo.tile_y;
   if (rb & 1)
-    step2_tile<T, EOS, BX, BIG, true>(fa, fb, geo, c, xs, y0, lds);
+    step2_tile<T, EOS, BX, BIG, true, false, 2>(fa, fb, geo, c, xs, y0, lds);
   else
-    step2_tile<T, EOS, BX, BIG, false>(fa, fb, geo, c, xs, y0, lds);
+    step2_tile<T, EOS, BX, BIG, false, false, 2>(fa, fb, geo, c, xs, y0, lds);
 }
 
 template <typename T, int EOS, bool BIG>

@@ -34,6 +34,12 @@
 // straight-line block each.  It pays where a workgroup's freed issue slots go
 // to other work at once (the persistent batch kernel); in per-step launches
 // the idle waves computing their wrapped duplicate columns measure faster.
+//
+// AHEAD is how many rows ahead of the first step's row the gathers run: 1, or
+// 2 with a third register set (nine more VGPRs, so four waves per SIMD in
+// FP32 instead of five); the second hides more of the loads' latency and
+// measures faster for the single lattice and the persistent batch launch,
+// the first for the per-step batch launches.
 #pragma once
 
 #include "lbm_tile.h"
@@ -53,7 +59,7 @@ struct Tile2Lds {
 template <int BX>
 constexpr int tile2_width() { return BX - 6; }
 
-template <typename T, int EOS, int BX, bool BIG, bool DOWN, bool SKIP = false>
+template <typename T, int EOS, int BX, bool BIG, bool DOWN, bool SKIP = false, int AHEAD = 1>
 __device__ __forceinline__ void step2_tile(const T* __restrict__ fa, T* __restrict__ fb,
                                            const Geometry& geo, const DevC<T>& c, int xs, int y0,
                                            Tile2Lds<T, BX>& L) {
@@ -169,7 +175,7 @@ __device__ __forceinline__ void step2_tile(const T* __restrict__ fa, T* __restri
       L.Fb[sb][2][l] = out[BH2];
     }
     // the previous row is done: its registers take the next row
-    if (i + 1 < n) gather_row(r0 + dr * (i + 1), prev);
+    if (i + AHEAD < n) gather_row(r0 + dr * (i + AHEAD), prev);
     __syncthreads();
     // ---- C: second-step density of row q = r - 2 dr: f_a(x, q) = f*_a(x - e_ax, q - e_ay).
     // Row q + dr was written in iteration i (Fa), q in i - 1 (Fs slot i & 1),
@@ -203,10 +209,31 @@ __device__ __forceinline__ void step2_tile(const T* __restrict__ fa, T* __restri
     }
   };
 
+  static_assert(AHEAD == 1 || AHEAD == 2, "rows gathered ahead: 1 or 2");
+  if constexpr (AHEAD == 1) {
 #pragma unroll 1
-  for (int i = 0; i < n; i += 2) {
-    iteration(i, P, rP, Q, rQ, R, rR, S, rS);
-    if (i + 1 < n) iteration(i + 1, Q, rQ, P, rP, S, rS, R, rR);
+    for (int i = 0; i < n; i += 2) {
+      iteration(i, P, rP, Q, rQ, R, rR, S, rS);
+      if (i + 1 < n) iteration(i + 1, Q, rQ, P, rP, S, rS, R, rR);
+    }
+  } else {
+    // a third register set for the first step's rows: three roles rotate
+    // (current, previous, two ahead) against the second step's two, so the
+    // loop body is written six times
+    T X[9];
+    T rX = T(0);
+#pragma unroll
+    for (int a = 0; a < 9; ++a) X[a] = T(0);
+    gather_row(r0 + dr, Q);  // row 1 (row 0 is in P; n >= 7)
+#pragma unroll 1
+    for (int i = 0; i < n; i += 6) {
+      iteration(i, P, rP, X, rX, R, rR, S, rS);
+      if (i + 1 < n) iteration(i + 1, Q, rQ, P, rP, S, rS, R, rR);
+      if (i + 2 < n) iteration(i + 2, X, rX, Q, rQ, R, rR, S, rS);
+      if (i + 3 < n) iteration(i + 3, P, rP, X, rX, S, rS, R, rR);
+      if (i + 4 < n) iteration(i + 4, Q, rQ, P, rP, R, rR, S, rS);
+      if (i + 5 < n) iteration(i + 5, X, rX, Q, rQ, S, rS, R, rR);
+    }
   }
 }
 
