@@ -54,9 +54,9 @@ FLOPS_PER_LU = 260  # FP arithmetic of one cell update in the single-step kernel
 # VALU issue utilisation of the same launches (SQ_INSTS_VALU against 256 CUs x
 # GRBM_GUI_ACTIVE / 8).  They hold for the kernel sources whose digest is
 # COUNTERS_SOURCE_DIGEST; for any other build they are reported as null.
-MEASURED_TRAFFIC = {("fp32", 256, 16): (768.4e6 + 615.2e6), ("fp64", 256, 69): (1344.7e6 + 1220.3e6)}
-MEASURED_VALU_ISSUE = {("fp32", 256, 16): 0.772, ("fp64", 256, 69): 0.456}
-COUNTERS_SOURCE_DIGEST = "99340658de7e9e0a"
+MEASURED_TRAFFIC = {("fp32", 256, 16): (768.8e6 + 615.4e6), ("fp64", 256, 69): (1352.8e6 + 1220.6e6)}
+MEASURED_VALU_ISSUE = {("fp32", 256, 16): 0.778, ("fp64", 256, 69): 0.430}
+COUNTERS_SOURCE_DIGEST = "2ed8c7bedc67b831"
 KERNEL_SOURCES = ("lbm_device.h", "lbm_internal.h", "lbm_tile.h", "lbm_tile2.h", "lbm_step.hip",
                   "../../include/lbm.h")  # the header fixes the state layout (plane gap)
 from paper_1412_7228_amd import workloads  # noqa: E402  (data only: loads no library)

@@ -16,11 +16,28 @@ template <> struct V2<float> { using t = float2; };
 template <> struct V2<double> { using t = double2; };
 
 // Working-precision reciprocal and square root.  FP32 uses the hardware
-// v_rcp_f32 / v_sqrt_f32 (1 ulp); FP64 uses correctly rounded operations.
+// v_rcp_f32 / v_sqrt_f32 (1 ulp).  FP64 refines the hardware estimates by
+// Newton-Raphson steps to within about one ulp, for the positive normal
+// arguments the update produces: the reciprocal by r <- r + r (1 - x r),
+// twice; the square root from y ~ 1/sqrt(x) by one coupled step on
+// s ~ sqrt(x), h ~ y/2 and two corrections s <- s + h (x - s^2).
 __device__ __forceinline__ float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ double rcp_(double x) { return 1.0 / x; }
+__device__ __forceinline__ double rcp_(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+  return __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+}
 __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
-__device__ __forceinline__ double sqrt_(double x) { return __builtin_sqrt(x); }
+__device__ __forceinline__ double sqrt_(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double s = x * y, h = 0.5 * y;
+  const double e = __builtin_fma(-s, h, 0.5);
+  s = __builtin_fma(s, e, s);
+  h = __builtin_fma(h, e, h);
+  s = __builtin_fma(__builtin_fma(-s, s, x), h, s);
+  s = __builtin_fma(__builtin_fma(-s, s, x), h, s);
+  return x == 0.0 ? 0.0 : s;  // the estimate of 1/sqrt(0) is infinite
+}
 
 // Constants of one step in working precision T.  Derived combinations are
 // formed on the host in FP64 and rounded once.
