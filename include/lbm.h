@@ -25,12 +25,12 @@
  *  - Host arrays are double precision, nx*ny values, row-major [y][x]
  *    (x fastest); they are read or written during the call and stay owned by
  *    the caller.
- *  - Device state: two distribution buffers (A/B), each 9 planes of
- *    ny rows of `pitch` elements (pitch = nx rounded up to 64), consecutive
- *    planes LBM_PLANE_GAP elements apart (plane stride ny * pitch +
- *    LBM_PLANE_GAP: the gap staggers the nine planes a row's update reads
- *    across HBM channels; planes exactly 2^k bytes apart collide), element type
- *    double (LBM_FP64) or float (LBM_FP32), plane index a = 0..8 in the
+ *  - Device state: two distribution buffers (A/B), each ny lattice rows of
+ *    9 * pitch elements (pitch = nx rounded up to 64): row y holds the rows
+ *    of the nine distribution planes back to back, so element (a, y, x) is at
+ *    (9 * y + a) * pitch + x (plane stride pitch, row stride 9 * pitch; a
+ *    row's update reads three such runs instead of 27 separate plane rows).
+ *    Element type double (LBM_FP64) or float (LBM_FP32), plane index a = 0..8 in the
  *    velocity order e_0=(0,0), e_1=(1,0), e_2=(0,1), e_3=(-1,0), e_4=(0,-1),
  *    e_5=(1,1), e_6=(-1,1), e_7=(-1,-1), e_8=(1,-1).  A buffer holds the
  *    post-collision distributions of the previous step before streaming (the
@@ -78,15 +78,16 @@ typedef enum {
   LBM_FIELD_F0 = 3   /* distribution f_a is LBM_FIELD_F0 + a, a = 0..8 */
 } lbm_field;
 
-/* Elements between the end of one distribution plane and the start of the next. */
-#define LBM_PLANE_GAP 1024
+/* Distribution planes of the D2Q9 state: element (a, y, x) of a buffer is at
+ * (LBM_Q * y + a) * pitch + x. */
+#define LBM_Q 9
 
 /* Problem statement: lattice size (Sec. 3.1.1), EOS and temperature
  * (Eq. 21, Eq. 29), mixing parameter A (Eq. 9), pressure-tensor
  * coefficient kappa (Eq. 23), relaxation rates (Eq. 2). */
 typedef struct {
-  int32_t nx, ny;     /* periodic lattice, each >= 3; one plane (ny * pitch +
-                         LBM_PLANE_GAP elements) must stay below 4 GiB             */
+  int32_t nx, ny;     /* periodic lattice, each >= 3; ny * pitch elements (one
+                         plane's worth) must stay below 4 GiB                       */
   int32_t eos;        /* lbm_eos                                                    */
   int32_t precision;  /* lbm_precision: element type of the distributions           */
   double a, b, R;     /* EOS constants (b*rho must stay below 1 for vdW/PR, 4 for CS) */
@@ -281,12 +282,11 @@ lbm_status lbm_load_state(lbm_ctx* ctx, const void* buf, size_t len);
 lbm_status lbm_sync(lbm_ctx* ctx);
 
 /* Current step count, the device pointer of the buffer that holds the
- * current state and its row pitch in elements (for callers that time or
- * inspect the device state; layout [9][ny][pitch] with plane stride
- * ny * pitch + LBM_PLANE_GAP elements, post-collision values before
- * streaming).  Each output may be NULL.  The buffer stays owned by the
- * context (or the caller, after lbm_create_ext) and stops being current at
- * the next step. */
+ * current state and its plane row pitch in elements (for callers that time
+ * or inspect the device state; layout [ny][9][pitch]: element (a, y, x) at
+ * (9 * y + a) * pitch + x, post-collision values before streaming).  Each
+ * output may be NULL.  The buffer stays owned by the context (or the
+ * caller, after lbm_create_ext) and stops being current at the next step. */
 lbm_status lbm_state_info(const lbm_ctx* ctx, int64_t* step, const void** f_cur, int32_t* pitch);
 
 /* ---------------------------------------------------------------------------

@@ -41,7 +41,7 @@ lbm_status fail(lbm_status s, const char* fmt, ...) {
                   #expr, hipGetErrorString(e_), __FILE__, __LINE__);                         \
   } while (0)
 
-constexpr uint64_t kStateMagic = 0x4c424d5053543031ull;  // "LBMPST01"
+constexpr uint64_t kStateMagic = 0x4c424d5053543032ull;  // "LBMPST02": rows interleaved
 
 struct StateHeader {
   uint64_t magic;
@@ -257,9 +257,12 @@ lbm_status validate(const lbm_params* p) {
   if (p->nx < 3 || p->ny < 3) return fail(LBM_EINVAL, "lattice %d x %d: each side must be >= 3", p->nx, p->ny);
   if (p->precision != LBM_FP64 && p->precision != LBM_FP32)
     return fail(LBM_EINVAL, "unknown precision %d", p->precision);
-  // one distribution plane must stay below 4 GiB (32-bit buffer offsets)
+  // one distribution plane's worth (ny * pitch elements) must stay below
+  // 4 GiB: it bounds the cell count for the 32-bit cell indices of the
+  // kernels, and a lattice row of the nine planes stays far below the 4 GiB
+  // of one buffer resource
   const unsigned long long plane_bytes =
-      ((unsigned long long)p->ny * ((p->nx + 63) / 64 * 64) + LBM_PLANE_GAP) * (p->precision == LBM_FP32 ? 4u : 8u);
+      (unsigned long long)p->ny * ((p->nx + 63) / 64 * 64) * (p->precision == LBM_FP32 ? 4u : 8u);
   if (plane_bytes >= (1ull << 32))
     return fail(LBM_EINVAL, "lattice %d x %d too large: one plane is %llu bytes (limit 4 GiB)",
                 p->nx, p->ny, plane_bytes);
@@ -291,9 +294,9 @@ uint64_t params_hash(const lbm_params& p) {
 
 int pitch_of(const lbm_params& p) { return (p.nx + 63) / 64 * 64; }
 
-// Elements from one plane to the next: the rows and the gap that staggers the
-// planes across HBM channels (LBM_PLANE_GAP, in lbm.h).
-long long plane_of(const lbm_params& p) { return (long long)p.ny * pitch_of(p) + LBM_PLANE_GAP; }
+// Elements of one distribution buffer: ny lattice rows, each the nine planes'
+// rows of pitch elements back to back (lbm.h).
+size_t state_elems(const lbm_params& p) { return (size_t)p.ny * 9 * pitch_of(p); }
 
 size_t elem_size(const lbm_params& p) { return p.precision == LBM_FP32 ? 4 : 8; }
 
@@ -336,7 +339,7 @@ Geometry make_geometry(const lbm_params& p, int tile_x, int tile_y, int width) {
   g.nx = p.nx;
   g.ny = p.ny;
   g.pitch = pitch_of(p);
-  g.plane = plane_of(p);
+  g.row = 9ll * g.pitch;
   g.tile_x = tile_x;
   g.tile_y = tile_y;
   g.nstrips = (g.nx + width - 1) / width;
@@ -456,7 +459,7 @@ lbm_status make_ctx(const lbm_params* p, void* stream, void* ba, void* bb, size_
   default_launch2(*p, &tx, &ty);
   set_geometry2(c, tx, ty);
   c->fuse = 2;
-  c->buf_bytes = 9 * (size_t)c->g.plane * elem_size(*p);
+  c->buf_bytes = state_elems(*p) * elem_size(*p);
   c->step = 0;
   c->cur = 0;
   c->stream = static_cast<hipStream_t>(stream);  // NULL is the HIP null stream
@@ -661,7 +664,7 @@ lbm_status lbm_laplace_fit(const double* dp, const double* R_e, int32_t n, doubl
 
 size_t lbm_buffer_bytes(const lbm_params* p) {
   if (validate(p) != LBM_OK) return 0;
-  return 9 * (size_t)plane_of(*p) * elem_size(*p);
+  return state_elems(*p) * elem_size(*p);
 }
 
 lbm_status lbm_create(const lbm_params* p, void* hip_stream, lbm_ctx** out) {
@@ -1258,9 +1261,9 @@ lbm_status lbm_batch_create(const lbm_params* params, int32_t n, void* hip_strea
     g.y_begin = 0;
     g.y_end = g.ny;
     g.pitch = pitch_of(params[d]);
-    g.plane = plane_of(params[d]);
-    const size_t bytes = (9 * (size_t)g.plane * es + 255) / 256 * 256;
-    if (9 * (size_t)g.plane * es >= (1ull << 32)) {
+    g.row = 9ll * g.pitch;
+    const size_t bytes = (state_elems(params[d]) * es + 255) / 256 * 256;
+    if (state_elems(params[d]) * es >= (1ull << 32)) {
       lbm_batch_destroy(b);
       return fail(LBM_EINVAL, "batch domain %d: a distribution buffer must stay below 4 GiB", d);
     }

@@ -230,11 +230,12 @@ __device__ __forceinline__ int wrap_(int v, int n) { return v < 0 ? v + n : (v >
 // The buffers hold the post-collision distributions of the previous step,
 // not yet streamed (the step kernel streams by pulling).  The distribution
 // f_a(x, y) of the current state therefore sits at (x - e_a, y - e_a) of
-// plane a.  Element index of f_a(x, y):
+// plane a.  Element index of f_a(x, y) (rows interleaved, plane a's part of
+// lattice row y starting at y * row + a * pitch):
 __device__ __forceinline__ long long state_index(const Geometry& g, int a, int x, int y) {
   const int ex = (a == 1 || a == 5 || a == 8) ? 1 : ((a == 3 || a == 6 || a == 7) ? -1 : 0);
   const int ey = (a == 2 || a == 5 || a == 6) ? 1 : ((a == 4 || a == 7 || a == 8) ? -1 : 0);
-  return a * g.plane + (long long)wrap_(y - ey, g.ny) * g.pitch + wrap_(x - ex, g.nx);
+  return (long long)wrap_(y - ey, g.ny) * g.row + (long long)a * g.pitch + wrap_(x - ex, g.nx);
 }
 
 }  // namespace lbm

@@ -10,10 +10,12 @@
 
 namespace lbm {
 
-// Lattice geometry and the launch shape of the fused step kernel.
+// Lattice geometry and the launch shape of the fused step kernel.  The state
+// is row-interleaved: lattice row y holds the nine planes' rows back to back,
+// so element (a, y, x) is at (9 y + a) * pitch + x.
 struct Geometry {
-  int nx, ny, pitch;       // elements; pitch = row stride of one plane
-  long long plane;         // ny * pitch elements
+  int nx, ny, pitch;       // elements; pitch = one plane's row (nx rounded up to 64)
+  long long row;           // 9 * pitch: elements from one lattice row to the next
   int tile_x, tile_y;      // strip width (= workgroup size) and rows per workgroup
   int nstrips, nrowblocks; // ceil(nx / tile_x), ceil((y_end - y_begin) / tile_y)
   int nblocks;             // nstrips * nrowblocks

@@ -43,9 +43,8 @@ static hipError_t launch_step_b(const Geometry& g, const DevC<T>& c, const void*
 template <typename T, int EOS>
 static hipError_t launch_step_t(const Geometry& g, const DevC<T>& c, const void* fa, void* fb,
                                 hipStream_t s) {
-  const unsigned long long bytes = 9ull * (unsigned long long)g.plane * sizeof(T);
+  const unsigned long long bytes = (unsigned long long)g.ny * g.row * sizeof(T);
   if (bytes < (1ull << 32)) return launch_step_b<T, EOS, false>(g, c, fa, fb, s);
-  if ((unsigned long long)g.plane * sizeof(T) >= (1ull << 32)) return hipErrorInvalidValue;
   return launch_step_b<T, EOS, true>(g, c, fa, fb, s);
 }
 
@@ -101,9 +100,8 @@ static hipError_t launch_step2_b(const Geometry& g, const DevC<T>& c, const void
 template <typename T, int EOS>
 static hipError_t launch_step2_t(const Geometry& g, const DevC<T>& c, const void* fa, void* fb,
                                  hipStream_t s) {
-  const unsigned long long bytes = 9ull * (unsigned long long)g.plane * sizeof(T);
+  const unsigned long long bytes = (unsigned long long)g.ny * g.row * sizeof(T);
   if (bytes < (1ull << 32)) return launch_step2_b<T, EOS, false>(g, c, fa, fb, s);
-  if ((unsigned long long)g.plane * sizeof(T) >= (1ull << 32)) return hipErrorInvalidValue;
   return launch_step2_b<T, EOS, true>(g, c, fa, fb, s);
 }
 
@@ -152,7 +150,7 @@ static hipError_t occupancy_t(int eos, int bx, bool big, int* per_cu) {
 
 hipError_t step_occupancy(lbm_precision prec, const Geometry& g, int eos, int* per_cu) {
   const size_t es = prec == LBM_FP32 ? 4 : 8;
-  const bool big = 9ull * (unsigned long long)g.plane * es >= (1ull << 32);
+  const bool big = (unsigned long long)g.ny * g.row * es >= (1ull << 32);
   if (prec == LBM_FP32) return occupancy_t<float>(eos, g.tile_x, big, per_cu);
   return occupancy_t<double>(eos, g.tile_x, big, per_cu);
 }

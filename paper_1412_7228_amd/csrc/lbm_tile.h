@@ -53,45 +53,64 @@ __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, unsigned voff, unsi
   }
 }
 
-// The distribution buffers as seen by the step kernel.  A buffer below 4 GiB
-// is one resource and the plane offset goes into the scalar offset; a larger
-// one gets one resource per plane.
+// The distribution buffers as seen by the step kernels.  Rows are
+// interleaved: lattice row y holds the nine planes' rows back to back (row
+// stride row_bytes, plane a at a * plane_bytes within it).  A buffer below
+// 4 GiB is one resource, with the row and plane offsets in the scalar
+// offset; a larger one gets a resource per lattice row, made when the row is
+// addressed (a row of nine planes stays below 4 GiB).
 template <bool BIG>
 struct Planes {
-  __amdgpu_buffer_rsrc_t r[BIG ? 9 : 1];
-  unsigned plane_bytes;
-  __device__ __forceinline__ void init(const void* base, unsigned long long plane_b) {
-    if constexpr (BIG) {
-#pragma unroll
-      for (int a = 0; a < 9; ++a)
-        r[a] = plane_rsrc(static_cast<const char*>(base) + a * plane_b, (unsigned)plane_b);
-    } else {
-      r[0] = plane_rsrc(base, (unsigned)(9 * plane_b));
-    }
-    plane_bytes = (unsigned)plane_b;
+  __amdgpu_buffer_rsrc_t r;  // the whole buffer (below 4 GiB)
+  const char* base;
+  unsigned plane_bytes, row_bytes;
+  struct Row {
+    __amdgpu_buffer_rsrc_t rs;
+    unsigned off;  // scalar byte offset of plane 0 of the row
+  };
+  __device__ __forceinline__ void init(const void* b, unsigned plane_b, unsigned row_b,
+                                       unsigned long long total_b) {
+    base = static_cast<const char*>(b);
+    plane_bytes = plane_b;
+    row_bytes = row_b;
+    if constexpr (!BIG) r = plane_rsrc(b, (unsigned)total_b);
   }
-  __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(int a) const { return r[BIG ? a : 0]; }
-  __device__ __forceinline__ unsigned soff(int a, unsigned row) const {
-    return BIG ? row : a * plane_bytes + row;
+  // lattice row y, 0 <= y < ny
+  __device__ __forceinline__ Row row(int y) const {
+    if constexpr (BIG) {
+      return Row{plane_rsrc(base + (unsigned long long)(unsigned)y * row_bytes, row_bytes), 0u};
+    } else {
+      return Row{r, (unsigned)y * row_bytes};
+    }
   }
 };
 
-// f_a(x - e_a) for the 9 velocities, gathered at row r.  rr, rm, rp are the
-// byte offsets of rows r, r - 1, r + 1 within a plane (uniform); ox, oxm, oxp
-// the byte offsets of columns x, x - 1, x + 1 (per lane).
+// f_a(x - e_a) for the 9 velocities, gathered at lattice row yr.  ym, yp are
+// rows yr - 1 and yr + 1 after the periodic wrap (uniform); ox, oxm, oxp the
+// byte offsets of columns x, x - 1, x + 1 (per lane).
 template <typename T, bool BIG>
-__device__ __forceinline__ void gather(const Planes<BIG>& pa, unsigned rr, unsigned rm,
-                                       unsigned rp, unsigned ox, unsigned oxm, unsigned oxp,
-                                       T (&g)[9]) {
-  g[0] = ld<T>(pa.rsrc(0), ox, pa.soff(0, rr));
-  g[1] = ld<T>(pa.rsrc(1), oxm, pa.soff(1, rr));  // e_1 = ( 1, 0)
-  g[2] = ld<T>(pa.rsrc(2), ox, pa.soff(2, rm));   // e_2 = ( 0, 1)
-  g[3] = ld<T>(pa.rsrc(3), oxp, pa.soff(3, rr));  // e_3 = (-1, 0)
-  g[4] = ld<T>(pa.rsrc(4), ox, pa.soff(4, rp));   // e_4 = ( 0,-1)
-  g[5] = ld<T>(pa.rsrc(5), oxm, pa.soff(5, rm));  // e_5 = ( 1, 1)
-  g[6] = ld<T>(pa.rsrc(6), oxp, pa.soff(6, rm));  // e_6 = (-1, 1)
-  g[7] = ld<T>(pa.rsrc(7), oxp, pa.soff(7, rp));  // e_7 = (-1,-1)
-  g[8] = ld<T>(pa.rsrc(8), oxm, pa.soff(8, rp));  // e_8 = ( 1,-1)
+__device__ __forceinline__ void gather(const Planes<BIG>& pa, int yr, int ym, int yp,
+                                       unsigned ox, unsigned oxm, unsigned oxp, T (&g)[9]) {
+  const auto R = pa.row(yr), M = pa.row(ym), P = pa.row(yp);
+  const unsigned pb = pa.plane_bytes;
+  g[0] = ld<T>(R.rs, ox, R.off);
+  g[1] = ld<T>(R.rs, oxm, R.off + pb);      // e_1 = ( 1, 0)
+  g[2] = ld<T>(M.rs, ox, M.off + 2 * pb);   // e_2 = ( 0, 1)
+  g[3] = ld<T>(R.rs, oxp, R.off + 3 * pb);  // e_3 = (-1, 0)
+  g[4] = ld<T>(P.rs, ox, P.off + 4 * pb);   // e_4 = ( 0,-1)
+  g[5] = ld<T>(M.rs, oxm, M.off + 5 * pb);  // e_5 = ( 1, 1)
+  g[6] = ld<T>(M.rs, oxp, M.off + 6 * pb);  // e_6 = (-1, 1)
+  g[7] = ld<T>(P.rs, oxp, P.off + 7 * pb);  // e_7 = (-1,-1)
+  g[8] = ld<T>(P.rs, oxm, P.off + 8 * pb);  // e_8 = ( 1,-1)
+}
+
+// The nine post-collision values of one cell, stored at lattice row y.
+template <typename T, bool BIG>
+__device__ __forceinline__ void store_row(const Planes<BIG>& pb, int y, unsigned ox,
+                                          const T (&out)[9]) {
+  const auto W = pb.row(y);
+#pragma unroll
+  for (int a = 0; a < 9; ++a) st<T>(W.rs, ox, W.off + a * pb.plane_bytes, out[a]);
 }
 
 // One tile: columns [x0, x0 + tile_x) x rows [y0, y0 + tile_y) (clipped to the
@@ -122,21 +141,19 @@ __device__ __forceinline__ void step_tile(const T* __restrict__ fa, T* __restric
   const unsigned ohxp = ((hx == nx - 1) ? 0 : hx + 1) * sz;
   const int hslot = (tx == 0) ? 0 : W + 1;
 
-  const unsigned row_bytes = (unsigned)(geo.pitch * sz);
   Planes<BIG> pa, pb;
-  pa.init(fa, (unsigned long long)geo.plane * sz);
-  pb.init(fb, (unsigned long long)geo.plane * sz);
+  const unsigned long long total = (unsigned long long)geo.ny * geo.row * sz;
+  pa.init(fa, geo.pitch * sz, (unsigned)(geo.row * sz), total);
+  pb.init(fb, geo.pitch * sz, (unsigned)(geo.row * sz), total);
 
   const int dr = down ? -1 : 1;
   const int r0 = down ? y0 + H : y0 - 1;
   const int n = H + 2;
   // the row offsets of row r: rr (r), rm (r - 1), rp (r + 1)
   auto gather_row = [&](int r, T(&g)[9], T(&h)[9]) {
-    const unsigned rr = wrap_(r, ny) * row_bytes;
-    const unsigned rm = wrap_(r - 1, ny) * row_bytes;
-    const unsigned rp = wrap_(r + 1, ny) * row_bytes;
-    gather(pa, rr, rm, rp, ox, oxm, oxp, g);
-    if (edge) gather(pa, rr, rm, rp, ohx, ohxm, ohxp, h);
+    const int yr = wrap_(r, ny), ym = wrap_(r - 1, ny), yp = wrap_(r + 1, ny);
+    gather(pa, yr, ym, yp, ox, oxm, oxp, g);
+    if (edge) gather(pa, yr, ym, yp, ohx, ohxm, ohxp, h);
   };
 
   T gn[9], hn[9];
@@ -180,9 +197,7 @@ __device__ __forceinline__ void step_tile(const T* __restrict__ fa, T* __restric
       v = ring[ss][tx + 2]; Un[8] = v.x; Pn[8] = v.y;  // ( 1,-1)
       T out[9];
       collide_cell(fc, rho_c, Un, Pn, c, out);
-      const unsigned ro = (unsigned)(r - dr) * row_bytes;
-#pragma unroll
-      for (int a = 0; a < 9; ++a) st<T>(pb.rsrc(a), ox, pb.soff(a, ro), out[a]);
+      store_row(pb, r - dr, ox, out);
     }
 #pragma unroll
     for (int a = 0; a < 9; ++a) fc[a] = g[a];

@@ -75,10 +75,10 @@ __device__ __forceinline__ void step2_tile(const T* __restrict__ fa, T* __restri
   const unsigned oxp = ((x == nx - 1) ? 0 : x + 1) * sz;
   const bool store = tx >= 3 && tx < BX - 3 && u < min(xs + tile2_width<BX>(), nx);
 
-  const unsigned row_bytes = (unsigned)(geo.pitch * sz);
   Planes<BIG> pa, pb;
-  pa.init(fa, (unsigned long long)geo.plane * sz);
-  pb.init(fb, (unsigned long long)geo.plane * sz);
+  const unsigned long long total = (unsigned long long)geo.ny * geo.row * sz;
+  pa.init(fa, geo.pitch * sz, (unsigned)(geo.row * sz), total);
+  pb.init(fb, geo.pitch * sz, (unsigned)(geo.row * sz), total);
 
   constexpr int dr = DOWN ? -1 : 1;
   const int r0 = DOWN ? y0 + H + 2 : y0 - 3;
@@ -96,10 +96,7 @@ __device__ __forceinline__ void step2_tile(const T* __restrict__ fa, T* __restri
     return m < 0 ? m + ny : m;
   };
   auto gather_row = [&](int r, T(&g)[9]) {
-    const unsigned rr = wrap_row(r) * row_bytes;
-    const unsigned rm = wrap_row(r - 1) * row_bytes;
-    const unsigned rp = wrap_row(r + 1) * row_bytes;
-    gather(pa, rr, rm, rp, ox, oxm, oxp, g);
+    gather(pa, wrap_row(r), wrap_row(r - 1), wrap_row(r + 1), ox, oxm, oxp, g);
   };
   // stencil of the centre row (slot s_mid) from the rows before (s_old) and
   // after (s_new) it in the march direction
@@ -201,11 +198,7 @@ __device__ __forceinline__ void step2_tile(const T* __restrict__ fa, T* __restri
       T Un[9], Pn[9], out[9];
       load_stencil(L.ring2, i % 3, (i - 1) % 3, (i - 2) % 3, Un, Pn);
       collide_cell(fc2, rc2, Un, Pn, c, out);
-      if (store) {
-        const unsigned ro = (unsigned)(r0 + dr * (i - 3)) * row_bytes;
-#pragma unroll
-        for (int a = 0; a < 9; ++a) st<T>(pb.rsrc(a), ox, pb.soff(a, ro), out[a]);
-      }
+      if (store) store_row(pb, r0 + dr * (i - 3), ox, out);
     }
   };
 

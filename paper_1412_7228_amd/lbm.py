@@ -20,7 +20,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbm.so")
-PLANE_GAP = 1024  # LBM_PLANE_GAP of include/lbm.h: elements between two distribution planes
+Q = 9  # LBM_Q of include/lbm.h: element (a, y, x) of a state buffer at (Q * y + a) * pitch + x
 
 EOS = {"ideal": 0, "cs": 1, "vdw": 2, "pr": 3}
 EOS_CONSTANTS = {
@@ -327,9 +327,9 @@ class Lattice:
         _check(self.lib.lbm_load_state(self.h, buf, len(blob)))
 
     def state_tensor(self):
-        """The current device state as a torch view [9, ny, pitch] with plane stride
-        ny * pitch + PLANE_GAP (the library's layout: post-collision values before
-        streaming), in the working precision.
+        """The current device state as a torch view [9, ny, pitch] over the library's
+        row-interleaved layout (plane stride pitch, row stride 9 * pitch; post-collision
+        values before streaming), in the working precision.
         Valid until the next step; writes to it change the state."""
         import torch
 
@@ -339,8 +339,7 @@ class Lattice:
         buf = next(b for b in self._bufs if b.data_ptr() == ptr)
         dt = torch.float32 if self.p.precision == PRECISION["fp32"] else torch.float64
         pitch = (self.nx + 63) // 64 * 64
-        plane = self.ny * pitch + PLANE_GAP
-        return buf.view(dt).as_strided((9, self.ny, pitch), (plane, pitch, 1))
+        return buf.view(dt).as_strided((Q, self.ny, pitch), (pitch, Q * pitch, 1))
 
     def info(self) -> dict:
         step, ptr, pitch = ctypes.c_int64(), ctypes.c_void_p(), ctypes.c_int32()

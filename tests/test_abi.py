@@ -76,14 +76,14 @@ def test_invalid_parameters_are_rejected_before_device_use(lib, bad):
 
 
 def test_buffer_bytes_pitch(lib):
-    """9 planes of ny rows of pitch elements (nx rounded up to 64), LBM_PLANE_GAP
-    elements apart; the binding's constant is the header's."""
-    m = re.search(r"#define\s+LBM_PLANE_GAP\s+(\d+)", open(os.path.join(ROOT, "include", "lbm.h")).read())
-    assert m and int(m.group(1)) == lbm.PLANE_GAP == 1024
+    """ny lattice rows, each the rows of the 9 planes back to back, pitch elements
+    each (nx rounded up to 64); the binding's constant is the header's."""
+    m = re.search(r"#define\s+LBM_Q\s+(\d+)", open(os.path.join(ROOT, "include", "lbm.h")).read())
+    assert m and int(m.group(1)) == lbm.Q == 9
     p = lbm.make_params(dict(nx=100, ny=7, precision="fp32"))
-    assert lib.lbm_buffer_bytes(ctypes.byref(p)) == 9 * (7 * 128 + 1024) * 4
+    assert lib.lbm_buffer_bytes(ctypes.byref(p)) == 7 * 9 * 128 * 4
     p = lbm.make_params(dict(nx=128, ny=3))
-    assert lib.lbm_buffer_bytes(ctypes.byref(p)) == 9 * (3 * 128 + 1024) * 8
+    assert lib.lbm_buffer_bytes(ctypes.byref(p)) == 3 * 9 * 128 * 8
 
 
 @pytest.mark.parametrize("eos", ["cs", "vdw", "pr"])
@@ -133,11 +133,11 @@ def test_caller_buffers_misaligned_or_short_are_rejected(lib, offset, nbytes):
 
 
 def test_largest_plane_is_accepted_and_one_more_row_is_not(lib):
-    """One distribution plane must stay below 4 GiB (32-bit offsets inside a plane): an
-    FP32 32768 x 32767 lattice (plane 4,294,840,320 bytes with the gap) is valid,
+    """One plane's worth of elements (ny * pitch) must stay below 4 GiB (it bounds the
+    cell count): an FP32 32768 x 32767 lattice (4,294,836,224 bytes a plane) is valid,
     32768 x 32768 is not."""
     ok = lbm.make_params(dict(nx=32768, ny=32767, precision="fp32"))
-    assert lib.lbm_buffer_bytes(ctypes.byref(ok)) == 9 * (32767 * 32768 + 1024) * 4
+    assert lib.lbm_buffer_bytes(ctypes.byref(ok)) == 9 * 32767 * 32768 * 4
     bad = lbm.make_params(dict(nx=32768, ny=32768, precision="fp32"))
     assert lib.lbm_buffer_bytes(ctypes.byref(bad)) == 0
     h = ctypes.c_void_p()
