@@ -504,7 +504,7 @@ def test_graph_replays_on_a_caller_stream(lbm):
 
 def test_buffer_above_4gib_equals_its_periodic_tile(lbm):
     """A lattice whose distribution buffer passes 4 GiB (12000 x 10200 FP32: 4.4 GB) runs
-    the kernel variant with one buffer resource per plane.  Its initial density repeats a
+    the kernel variant with one buffer resource per lattice row.  Its initial density repeats a
     120 x 102 tile 100 x 100 times; the update is local and translation-invariant, so
     after two launches every tile must equal the 120 x 102 lattice run alone, bit for bit."""
     say("12000 x 10200 fp32 (buffer > 4 GiB) vs its 120 x 102 tile")
