@@ -502,14 +502,16 @@ def test_graph_replays_on_a_caller_stream(lbm):
         assert np.array_equal(a.f_soa(), b.f_soa()), steps
 
 
-def test_buffer_above_4gib_equals_its_periodic_tile(lbm):
-    """A lattice whose distribution buffer passes 4 GiB (12000 x 10200 FP32: 4.4 GB) runs
-    the kernel variant with one buffer resource per lattice row.  Its initial density repeats a
-    120 x 102 tile 100 x 100 times; the update is local and translation-invariant, so
-    after two launches every tile must equal the 120 x 102 lattice run alone, bit for bit."""
-    say("12000 x 10200 fp32 (buffer > 4 GiB) vs its 120 x 102 tile")
-    tx, ty, k = 120, 102, 100
-    cfg = dict(eos="cs", T_over_Tc=0.7, A=-0.5, kappa=0.3, precision="fp32")
+@pytest.mark.parametrize("precision,tx,ty", [("fp32", 120, 102), ("fp64", 78, 78)])
+def test_buffer_above_4gib_equals_its_periodic_tile(lbm, precision, tx, ty):
+    """A lattice whose distribution buffer passes 4 GiB (12000 x 10200 FP32, 7800 x 7800
+    FP64: 4.4 GB each) runs the kernel variant with one buffer resource per lattice row.
+    Its initial density repeats a tx x ty tile 100 x 100 times; the update is local and
+    translation-invariant, so after two launches every tile must equal the tile lattice
+    run alone, bit for bit."""
+    k = 100
+    say(f"{tx * k} x {ty * k} {precision} (buffer > 4 GiB) vs its {tx} x {ty} tile")
+    cfg = dict(eos="cs", T_over_Tc=0.7, A=-0.5, kappa=0.3, precision=precision)
     small_rho = inputs.spinodal(tx, ty, 0.183713, noise=1e-2, seed=12)
     small = lbm.Lattice(dict(cfg, nx=tx, ny=ty))
     small.init_field(small_rho)
