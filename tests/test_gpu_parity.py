@@ -221,6 +221,39 @@ def test_nonfinite_initial_density_rejected(lbm):
     assert ei.value.status == -6
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_device_state_layout_is_the_headers(lbm, precision):
+    """The device buffer holds, for plane a of the D2Q9 set (e_0..e_8 in the header's order),
+    the post-collision value of the cell that streams into (x, y) at element
+    (9 y + a) * pitch + x', x' = x - e_ax, y' = y - e_ay (periodic), as include/lbm.h states:
+    read the raw buffer by that formula (not through the binding's strided view) and compare
+    with the streamed distributions the library reads back.  A 70 x 5 lattice (pitch 128,
+    so the padding columns are skipped) after 3 steps."""
+    import torch
+
+    say(f"device state layout, 70 x 5 {precision}")
+    ex = [0, 1, 0, -1, 0, 1, -1, -1, 1]
+    ey = [0, 0, 1, 0, -1, 1, 1, -1, -1]
+    nx, ny = 70, 5
+    lat = lbm.Lattice(dict(nx=nx, ny=ny, eos="cs", T_over_Tc=0.8, precision=precision))
+    lat.init_field(inputs.spinodal(nx, ny, 0.2, noise=1e-2, seed=4))
+    lat.step(3)
+    f = lat.f_soa()
+    info = lat.info()
+    pitch = info["pitch"]
+    assert pitch == 128
+    buf = next(b for b in lat._bufs if b.data_ptr() == info["f_cur"])
+    dt = torch.float32 if precision == "fp32" else torch.float64
+    raw = buf.view(dt).cpu().numpy().astype(np.float64)
+    assert raw.size == ny * 9 * pitch
+    for a in range(9):
+        for y in range(ny):
+            for x in range(nx):
+                xs, ys = (x - ex[a]) % nx, (y - ey[a]) % ny
+                assert raw[(9 * ys + a) * pitch + xs] == f[a, y, x], (a, x, y)
+    lat.close()
+
+
 def test_checkpoint_resume_is_bitwise(lbm):
     say("checkpoint 96x80 fp32")
     rv, rl = cs_maxwell(0.7)
