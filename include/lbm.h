@@ -87,7 +87,8 @@ typedef enum {
  * coefficient kappa (Eq. 23), relaxation rates (Eq. 2). */
 typedef struct {
   int32_t nx, ny;     /* periodic lattice, each >= 3; ny * pitch elements (one
-                         plane's worth) must stay below 4 GiB                       */
+                         plane's worth) and 9 * pitch elements (one lattice row of
+                         the nine planes) must each stay below 4 GiB                */
   int32_t eos;        /* lbm_eos                                                    */
   int32_t precision;  /* lbm_precision: element type of the distributions           */
   double a, b, R;     /* EOS constants (b*rho must stay below 1 for vdW/PR, 4 for CS) */

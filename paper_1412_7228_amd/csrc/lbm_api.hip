@@ -259,13 +259,17 @@ lbm_status validate(const lbm_params* p) {
     return fail(LBM_EINVAL, "unknown precision %d", p->precision);
   // one distribution plane's worth (ny * pitch elements) must stay below
   // 4 GiB: it bounds the cell count for the 32-bit cell indices of the
-  // kernels, and a lattice row of the nine planes stays far below the 4 GiB
-  // of one buffer resource
-  const unsigned long long plane_bytes =
-      (unsigned long long)p->ny * ((p->nx + 63) / 64 * 64) * (p->precision == LBM_FP32 ? 4u : 8u);
+  // kernels; and one lattice row of the nine planes (9 * pitch elements) must
+  // too: the kernels address a row with 32-bit offsets
+  const unsigned es = p->precision == LBM_FP32 ? 4u : 8u;
+  const unsigned long long pitch = (unsigned long long)(p->nx + 63) / 64 * 64;
+  const unsigned long long plane_bytes = (unsigned long long)p->ny * pitch * es;
   if (plane_bytes >= (1ull << 32))
     return fail(LBM_EINVAL, "lattice %d x %d too large: one plane is %llu bytes (limit 4 GiB)",
                 p->nx, p->ny, plane_bytes);
+  if (9ull * pitch * es >= (1ull << 32))
+    return fail(LBM_EINVAL, "lattice %d x %d too wide: one row of the nine planes is %llu bytes (limit 4 GiB)",
+                p->nx, p->ny, 9ull * pitch * es);
   if (p->eos < LBM_EOS_IDEAL || p->eos > LBM_EOS_PR) return fail(LBM_EINVAL, "unknown EOS %d", p->eos);
   const double rates[4] = {p->s_e, p->s_eps, p->s_q, p->s_nu};
   for (double s : rates)

@@ -143,6 +143,13 @@ def test_largest_plane_is_accepted_and_one_more_row_is_not(lib):
     h = ctypes.c_void_p()
     assert lib.lbm_create(ctypes.byref(bad), None, ctypes.byref(h)) == -1
     assert b"4 GiB" in lib.lbm_last_error()
+    # a narrow plane but a lattice row of the nine planes past 4 GiB (32-bit row offsets):
+    # 119,304,704 FP32 columns (a multiple of 64) are the first whose row reaches 4 GiB
+    for nx, ok_row in ((119_304_640, True), (119_304_704, False)):
+        p = lbm.make_params(dict(nx=nx, ny=3, precision="fp32"))
+        assert (lib.lbm_buffer_bytes(ctypes.byref(p)) != 0) == ok_row, nx
+    assert lib.lbm_create(ctypes.byref(p), None, ctypes.byref(h)) == -1
+    assert b"too wide" in lib.lbm_last_error()
 
 
 def test_library_laplace_fit_matches_oracle(lib, oracle_mod):
