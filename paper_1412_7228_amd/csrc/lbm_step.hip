@@ -61,11 +61,18 @@ static hipError_t launch_step_p(const Geometry& g, const ModelConsts& m, const v
   }
 }
 
+// Rows gathered ahead by the two-step kernel (AHEAD of step2_tile) and the
+// FP32 waves per SIMD that fit its registers: 256-lane strips gather two rows
+// ahead at four waves per SIMD; 128-lane strips, the default of small and
+// slab-shaped lattices whose grids are a few thousand workgroups, one row
+// ahead at five (two rows ahead costs them about a tenth: 4096 x 520 in
+// 128 x 8 tiles, 46 against 42 us per launch).
+template <typename T, int BX>
+constexpr int step2_ahead() { return (sizeof(T) == 4 && BX == 128) ? 1 : 2; }
+
 // Two fused steps over the whole lattice; the same workgroup-to-tile order.
-// Gathers two rows ahead (AHEAD = 2 of step2_tile); FP32: at most 128 VGPRs,
-// four waves per SIMD.
 template <typename T, int EOS, int BX, bool BIG>
-__global__ void __launch_bounds__(BX, sizeof(T) == 4 ? 4 : 1) k_step2(const T* __restrict__ fa, T* __restrict__ fb,
+__global__ void __launch_bounds__(BX, sizeof(T) == 4 ? (BX == 128 ? 5 : 4) : 1) k_step2(const T* __restrict__ fa, T* __restrict__ fb,
                                                const Geometry geo, const DevC<T> c) {
   __shared__ Tile2Lds<T, BX> lds;
   static_assert(tile2_width<BX>() == BX - kStep2Halo, "strip width");
@@ -74,9 +81,9 @@ __global__ void __launch_bounds__(BX, sizeof(T) == 4 ? 4 : 1) k_step2(const T* _
   const int strip = lb - rb * geo.nstrips;
   const int xs = strip * tile2_width<BX>(), y0 = geo.y_begin + rb * geo.tile_y;
   if (rb & 1)
-    step2_tile<T, EOS, BX, BIG, true, false, 2>(fa, fb, geo, c, xs, y0, lds);
+    step2_tile<T, EOS, BX, BIG, true, false, step2_ahead<T, BX>()>(fa, fb, geo, c, xs, y0, lds);
   else
-    step2_tile<T, EOS, BX, BIG, false, false, 2>(fa, fb, geo, c, xs, y0, lds);
+    step2_tile<T, EOS, BX, BIG, false, false, step2_ahead<T, BX>()>(fa, fb, geo, c, xs, y0, lds);
 }
 
 template <typename T, int EOS, bool BIG>
