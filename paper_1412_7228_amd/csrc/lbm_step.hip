@@ -61,18 +61,18 @@ static hipError_t launch_step_p(const Geometry& g, const ModelConsts& m, const v
   }
 }
 
-// Rows gathered ahead by the two-step kernel (AHEAD of step2_tile) and the
-// FP32 waves per SIMD that fit its registers: 256-lane strips gather two rows
-// ahead at four waves per SIMD; 128-lane strips, the default of small and
-// slab-shaped lattices whose grids are a few thousand workgroups, one row
-// ahead at five (two rows ahead costs them about a tenth: 4096 x 520 in
-// 128 x 8 tiles, 46 against 42 us per launch).
-template <typename T, int BX>
-constexpr int step2_ahead() { return (sizeof(T) == 4 && BX == 128) ? 1 : 2; }
+// Rows gathered ahead by the two-step kernel (AHEAD of step2_tile): FP32 one
+// row, which fits five waves per SIMD (96 VGPRs); FP64 two rows (two waves per
+// SIMD either way).  Measured on the row-interleaved layout, alternating
+// builds: FP32 one row ahead at five waves is 0.3% faster than two rows ahead
+// at four on 4096^2 at steps 200-2200, 2.7% at steps 5-25, and 10% on a
+// 4096 x 520 slab in 128 x 8 tiles; FP64 two rows ahead 1% faster than one.
+template <typename T>
+constexpr int step2_ahead() { return sizeof(T) == 4 ? 1 : 2; }
 
 // Two fused steps over the whole lattice; the same workgroup-to-tile order.
 template <typename T, int EOS, int BX, bool BIG>
-__global__ void __launch_bounds__(BX, sizeof(T) == 4 ? (BX == 128 ? 5 : 4) : 1) k_step2(const T* __restrict__ fa, T* __restrict__ fb,
+__global__ void __launch_bounds__(BX, sizeof(T) == 4 ? 5 : 1) k_step2(const T* __restrict__ fa, T* __restrict__ fb,
                                                const Geometry geo, const DevC<T> c) {
   __shared__ Tile2Lds<T, BX> lds;
   static_assert(tile2_width<BX>() == BX - kStep2Halo, "strip width");
@@ -81,9 +81,9 @@ __global__ void __launch_bounds__(BX, sizeof(T) == 4 ? (BX == 128 ? 5 : 4) : 1) 
   const int strip = lb - rb * geo.nstrips;
   const int xs = strip * tile2_width<BX>(), y0 = geo.y_begin + rb * geo.tile_y;
   if (rb & 1)
-    step2_tile<T, EOS, BX, BIG, true, false, step2_ahead<T, BX>()>(fa, fb, geo, c, xs, y0, lds);
+    step2_tile<T, EOS, BX, BIG, true, false, step2_ahead<T>()>(fa, fb, geo, c, xs, y0, lds);
   else
-    step2_tile<T, EOS, BX, BIG, false, false, step2_ahead<T, BX>()>(fa, fb, geo, c, xs, y0, lds);
+    step2_tile<T, EOS, BX, BIG, false, false, step2_ahead<T>()>(fa, fb, geo, c, xs, y0, lds);
 }
 
 template <typename T, int EOS, bool BIG>
