@@ -54,9 +54,9 @@ FLOPS_PER_LU = 260  # FP arithmetic of one cell update in the single-step kernel
 # VALU issue utilisation of the same launches (SQ_INSTS_VALU against 256 CUs x
 # GRBM_GUI_ACTIVE / 8).  They hold for the kernel sources whose digest is
 # COUNTERS_SOURCE_DIGEST; for any other build they are reported as null.
-MEASURED_TRAFFIC = {("fp32", 256, 16): (763.9e6 + 617.6e6), ("fp64", 256, 69): (1347.9e6 + 1220.3e6)}
-MEASURED_VALU_ISSUE = {("fp32", 256, 16): 0.840, ("fp64", 256, 69): 0.439}
-COUNTERS_SOURCE_DIGEST = "41e0e018b71f91b9"
+MEASURED_TRAFFIC = {("fp32", 256, 16): (763.2e6 + 617.5e6), ("fp64", 256, 69): (1347.1e6 + 1220.2e6)}
+MEASURED_VALU_ISSUE = {("fp32", 256, 16): 0.831, ("fp64", 256, 69): 0.436}
+COUNTERS_SOURCE_DIGEST = "d368bae567480736"
 KERNEL_SOURCES = ("lbm_device.h", "lbm_internal.h", "lbm_tile.h", "lbm_tile2.h", "lbm_step.hip",
                   "../../include/lbm.h")  # the header fixes the state layout
 from paper_1412_7228_amd import workloads  # noqa: E402  (data only: loads no library)

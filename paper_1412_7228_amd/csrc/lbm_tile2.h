@@ -37,9 +37,9 @@
 //
 // AHEAD is how many rows ahead of the first step's row the gathers run: 1, or
 // 2 with a third register set (nine more VGPRs, so four waves per SIMD in
-// FP32 instead of five); the second hides more of the loads' latency and
-// measures faster for the single lattice and the persistent batch launch,
-// the first for the per-step batch launches.
+// FP32 instead of five).  The second hides more of the loads' latency, the
+// first keeps more waves; each kernel takes the one that measures faster for
+// it (the launches state which).
 #pragma once
 
 #include "lbm_tile.h"
